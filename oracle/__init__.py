@@ -1,0 +1,194 @@
+"""CPU oracle for the Kawasaki lattice sweeps -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+this package never imports the product.  The arithmetic lives in
+``kk_oracle.c`` (plain C, built with gcc by :func:`build`); this module only
+marshals numpy arrays into it.  ``enumerate4x4`` is the one pure-Python
+helper: it lists all states of a small lattice for exact Boltzmann sums.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from itertools import combinations
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kk_oracle.c")
+_LIB = os.path.join(_HERE, "libkkoracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``kk_oracle.c`` into ``libkkoracle.so`` with gcc (OpenMP on)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-Wextra",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u16p = ctypes.POINTER(ctypes.c_uint16)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    c_int_p = ctypes.POINTER(ctypes.c_int)
+    U32, U64, D = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "ko_philox4x32_10": (None, [u32p, u32p, u32p]),
+        "ko_thresholds": (None, [D, u64p]),
+        "ko_sweep_randoms": (None, [U32, U64, U64, u16p]),
+        "ko_ext_word": (U32, [U64, U64, U32, U32]),
+        "ko_phase_order": (None, [U64, U64, c_int_p]),
+        "ko_site_class": (ctypes.c_int, [U32, U32]),
+        "ko_local_dnab": (ctypes.c_int, [u8p, U32, U32, U32, U32]),
+        "ko_lattice_hash": (U64, [u8p, U32]),
+        "ko_sweeps": (U64, [u8p, U32, D, U64, U64, U64, u64p]),
+        "ko_energy": (U64, [u8p, U32]),
+        "ko_n_ones": (U64, [U32, D]),
+        "ko_init_key": (U64, [U64, U32, U32]),
+        "ko_init": (ctypes.c_int, [u8p, U32, D, U64]),
+        "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
+        "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _lattice(s: np.ndarray) -> np.ndarray:
+    if s.dtype != np.uint8 or s.ndim != 2 or s.shape[0] != s.shape[1] or not s.flags.c_contiguous:
+        raise ValueError("lattice must be a C-contiguous square uint8 array")
+    return s
+
+
+# --------------------------------------------------------------------------
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().ko_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def thresholds(omega: float) -> np.ndarray:
+    T = np.zeros(7, dtype=np.uint64)
+    _load().ko_thresholds(float(omega), _ptr(T, ctypes.c_uint64))
+    return T
+
+
+def sweep_randoms(L: int, seed: int, t: int) -> np.ndarray:
+    """(L, L) uint16 array, per site (direction << 10) | u10 for sweep t."""
+    r = np.zeros((L, L), dtype=np.uint16)
+    _load().ko_sweep_randoms(L, seed, t, _ptr(r, ctypes.c_uint16))
+    return r
+
+
+def ext_word(seed: int, t: int, x: int, y: int) -> int:
+    return int(_load().ko_ext_word(seed, t, x, y))
+
+
+def phase_order(seed: int, t: int) -> list:
+    p = (ctypes.c_int * 8)()
+    _load().ko_phase_order(seed, t, p)
+    return list(p)
+
+
+def site_class(x: int, y: int) -> int:
+    return int(_load().ko_site_class(x, y))
+
+
+def local_dnab(s: np.ndarray, x: int, y: int, direction: int) -> int:
+    s = _lattice(s)
+    return int(_load().ko_local_dnab(_ptr(s, ctypes.c_uint8), s.shape[0], x, y, direction))
+
+
+def lattice_hash(s: np.ndarray) -> int:
+    s = _lattice(s)
+    return int(_load().ko_lattice_hash(_ptr(s, ctypes.c_uint8), s.shape[0]))
+
+
+def sweeps(s: np.ndarray, omega: float, seed: int, t0: int, n: int, trace: bool = False):
+    """Run n sweeps in place from sweep counter t0.
+
+    Returns the accepted-exchange count, or (count, per-sweep hashes)."""
+    s = _lattice(s)
+    L = s.shape[0]
+    tr = np.zeros(max(n, 1), dtype=np.uint64) if trace else None
+    acc = _load().ko_sweeps(_ptr(s, ctypes.c_uint8), L, float(omega), seed, t0, n,
+                            _ptr(tr, ctypes.c_uint64) if trace else None)
+    if acc == 2**64 - 1:
+        raise MemoryError("oracle sweep allocation failed")
+    return (int(acc), tr[:n]) if trace else int(acc)
+
+
+def energy(s: np.ndarray) -> int:
+    s = _lattice(s)
+    return int(_load().ko_energy(_ptr(s, ctypes.c_uint8), s.shape[0]))
+
+
+def n_ones(L: int, composition: float) -> int:
+    return int(_load().ko_n_ones(L, float(composition)))
+
+
+def init_key(seed: int, x: int, y: int) -> int:
+    return int(_load().ko_init_key(seed, x, y))
+
+
+def init(L: int, composition: float, seed: int) -> np.ndarray:
+    s = np.zeros((L, L), dtype=np.uint8)
+    if _load().ko_init(_ptr(s, ctypes.c_uint8), L, float(composition), seed) != 0:
+        raise MemoryError("oracle init allocation failed")
+    return s
+
+
+def cluster_counts(s: np.ndarray, species: int = 1) -> np.ndarray:
+    """Dense counts: out[k] = number of clusters of exactly k sites."""
+    s = _lattice(s)
+    L = s.shape[0]
+    counts = np.zeros(L * L + 1, dtype=np.uint64)
+    r = _load().ko_cluster_counts(_ptr(s, ctypes.c_uint8), L, int(species), _ptr(counts, ctypes.c_uint64))
+    if r == 2**64 - 1:
+        raise MemoryError("oracle cluster allocation failed")
+    return counts
+
+
+def cluster_hist(s: np.ndarray, species: int = 1):
+    """Sparse histogram: list of (size, count) pairs, ascending by size."""
+    c = cluster_counts(s, species)
+    nz = np.nonzero(c)[0]
+    return [(int(k), int(c[k])) for k in nz]
+
+
+def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:
+    s = _lattice(s)
+    return int(_load().ko_seq_kawasaki(_ptr(s, ctypes.c_uint8), s.shape[0], float(omega), rng_seed, n_steps))
+
+
+def enumerate_states(L: int, n1: int):
+    """All (L, L) 0/1 lattices with exactly n1 ones, as an (M, L*L) uint8 array."""
+    N = L * L
+    combos = list(combinations(range(N), n1))
+    out = np.zeros((len(combos), N), dtype=np.uint8)
+    for i, c in enumerate(combos):
+        out[i, list(c)] = 1
+    return out

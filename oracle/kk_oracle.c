@@ -1,0 +1,571 @@
+/*
+ * kk_oracle.c -- plain CPU oracle for Metropolis-Kawasaki exchange sweeps on
+ * a periodic square lattice holding a binary (A/B) lipid mixture.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the HIP implementation.
+ *
+ * What it follows (paper: Lis & Pintal, "GPU-Based Massive Parallel Kawasaki
+ * Kinetics in Monte Carlo Modelling of Lipid Microdomains"):
+ *   - Metropolis acceptance, u ~ U[0,1), accept iff u < min{1, p(x*)/p(x)}
+ *     with a symmetric proposal (Materials and Methods, "Monte Carlo model
+ *     with Kawasaki based kinetics", the numbered Metropolis algorithm);
+ *   - Kawasaki kinetics: a move swaps two nearest-neighbour lipids, so the
+ *     number of lipids of each type never changes (same section);
+ *   - the one-parameter Almeida interaction omega_AB = g_AB - (g_AA+g_BB)/2,
+ *     so E/kT = omega * N_AB + const (same section, the omega_AB equation);
+ *   - the MPKK loop: each step is a sequence of decompositions of the lattice
+ *     into disjoint domains; in each, every domain centre makes one Kawasaki
+ *     attempt at once; one step makes as many attempts as there are sites
+ *     (section "Massive Parallel Kawasaki Kinetics", the MPKK algorithm);
+ *   - cluster sizes of one lipid species (section "Cluster Analysis methods").
+ *
+ * Readings taken where the paper does not fix the computation (square
+ * periodic lattice instead of the triangular helical one, the 8-class
+ * conflict-free decomposition, the Philox random-number layout, the
+ * 42-bit acceptance threshold) are the contract written out in the
+ * functions below; each function says which one it implements.
+ *
+ * Parity pins: Philox against the published known-answer vectors; the
+ * local energy change against a full recount; conflict-freedom by brute
+ * force; stationarity against exact Boltzmann enumeration on 4x4; omega = 0
+ * pair statistics against the random-mixing closed form; 50:50 equilibrium
+ * against Onsager's nearest-neighbour correlation; the sweep against an
+ * independent sequential random-site Kawasaki chain; cluster histograms
+ * against scipy's labelling with a periodic merge.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KO_TAG_SWEEP 1u
+#define KO_TAG_EXT 2u
+#define KO_TAG_ORDER 3u
+#define KO_TAG_INIT 4u
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies; the    */
+/* two-word key is bumped by the Weyl constants between rounds.             */
+/* ---------------------------------------------------------------------- */
+void ko_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    int round;
+    for (round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+static void seed_to_key(uint64_t seed, uint32_t key[2])
+{
+    key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    key[1] = (uint32_t)(seed >> 32);
+}
+
+/* Fourth counter word: the sweep's high 28 bits and a 4-bit stream tag. */
+static uint32_t ctr3(uint64_t t, uint32_t tag)
+{
+    return (uint32_t)((t >> 32) & 0x0FFFFFFFu) | (tag << 28);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Acceptance thresholds.  For an exchange of an unlike pair whose two     */
+/* sites have n unlike neighbours in total (not counting each other), the  */
+/* number of AB contacts changes by dU = 6 - 2n, the energy by omega*dU,   */
+/* and the Metropolis probability is p = min(1, exp(-omega*dU)).  The      */
+/* contract draws u as a 42-bit integer U and accepts iff U < T[n] with    */
+/* T[n] = min(2^42, ceil(p * 2^42)), which is exactly U / 2^42 < p.        */
+/* ---------------------------------------------------------------------- */
+void ko_thresholds(double omega, uint64_t T[7])
+{
+    const double two42 = 4398046511104.0; /* 2^42 */
+    int n;
+    for (n = 0; n <= 6; ++n) {
+        double dU = 6.0 - 2.0 * (double)n;
+        double p = exp(-omega * dU);
+        double scaled = ceil(p * two42);
+        if (!(scaled < two42)) /* also catches +inf */
+            T[n] = (uint64_t)1 << 42;
+        else
+            T[n] = (uint64_t)scaled;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sweep random field.  Row y is cut into 32-site segments g; for sweep t  */
+/* the segment draws three Philox blocks with counters                     */
+/*   (y, 4g + j, t_lo, t_hi28 | TAG_SWEEP<<28),  j = 0, 1, 2,              */
+/* giving twelve 32-bit words P[4j + m] = block_j[m].  Bit b of word P[k]  */
+/* belongs to site x = 32g + b: direction = P0_b + 2*P1_b (0:+x 1:-x 2:+y  */
+/* 3:-y), and the 10-bit uniform prefix has P2_b as its most significant   */
+/* bit down to P11_b.  Here the field is stored per site as                */
+/* (direction << 10) | u10.                                               */
+/* ---------------------------------------------------------------------- */
+void ko_sweep_randoms(uint32_t L, uint64_t seed, uint64_t t, uint16_t *r)
+{
+    uint32_t key[2], y, g, G = (L + 31u) / 32u;
+    seed_to_key(seed, key);
+    for (y = 0; y < L; ++y) {
+        for (g = 0; g < G; ++g) {
+            uint32_t P[12], b;
+            int j;
+            for (j = 0; j < 3; ++j) {
+                uint32_t ctr[4];
+                ctr[0] = y;
+                ctr[1] = 4u * g + (uint32_t)j;
+                ctr[2] = (uint32_t)t;
+                ctr[3] = ctr3(t, KO_TAG_SWEEP);
+                ko_philox4x32_10(ctr, key, &P[4 * j]);
+            }
+            for (b = 0; b < 32u; ++b) {
+                uint32_t x = 32u * g + b, dir, u = 0;
+                int k;
+                if (x >= L)
+                    break;
+                dir = ((P[0] >> b) & 1u) | (((P[1] >> b) & 1u) << 1);
+                for (k = 0; k < 10; ++k)
+                    u = (u << 1) | ((P[2 + k] >> b) & 1u);
+                r[(size_t)y * L + x] = (uint16_t)((dir << 10) | u);
+            }
+        }
+    }
+}
+
+/* The 32 low-order bits of a site's 42-bit uniform, drawn only when the  */
+/* 10-bit prefix alone cannot decide: word (x mod 4) of Philox block      */
+/* (y, x div 4, t_lo, t_hi28 | TAG_EXT<<28).                               */
+uint32_t ko_ext_word(uint64_t seed, uint64_t t, uint32_t x, uint32_t y)
+{
+    uint32_t key[2], ctr[4], out[4];
+    seed_to_key(seed, key);
+    ctr[0] = y;
+    ctr[1] = x >> 2;
+    ctr[2] = (uint32_t)t;
+    ctr[3] = ctr3(t, KO_TAG_EXT);
+    ko_philox4x32_10(ctr, key, out);
+    return out[x & 3u];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Decomposition classes.  The paper tiles its triangular lattice with     */
+/* 7-site domains and picks one of the 7 coverings at random per           */
+/* iteration.  On the square lattice the contract uses 8 classes           */
+/*   class(x, y) = 2*((x - y) mod 4) + (y mod 2);                          */
+/* same-class sites are at L1 distance >= 4, so the exchanges of one class */
+/* touch disjoint neighbourhoods and may run in any order.  Each sweep     */
+/* visits the 8 classes in a random order (every site is a centre once,    */
+/* N attempts per sweep): Fisher-Yates over 8 entries driven by two Philox */
+/* blocks (0, j, t_lo, t_hi28 | TAG_ORDER<<28), j = 0, 1; step i = 7..1     */
+/* uses word w[7 - i] and swaps entry i with entry (w * (i + 1)) >> 32.    */
+/* ---------------------------------------------------------------------- */
+void ko_phase_order(uint64_t seed, uint64_t t, int perm[8])
+{
+    uint32_t key[2], w[8];
+    int i, j;
+    seed_to_key(seed, key);
+    for (j = 0; j < 2; ++j) {
+        uint32_t ctr[4];
+        ctr[0] = 0;
+        ctr[1] = (uint32_t)j;
+        ctr[2] = (uint32_t)t;
+        ctr[3] = ctr3(t, KO_TAG_ORDER);
+        ko_philox4x32_10(ctr, key, &w[4 * j]);
+    }
+    for (i = 0; i < 8; ++i)
+        perm[i] = i;
+    for (i = 7; i >= 1; --i) {
+        uint32_t pick = (uint32_t)(((uint64_t)w[7 - i] * (uint64_t)(i + 1)) >> 32);
+        int tmp = perm[i];
+        perm[i] = perm[pick];
+        perm[pick] = tmp;
+    }
+}
+
+int ko_site_class(uint32_t x, uint32_t y)
+{
+    return (int)(2u * ((x - y) & 3u) + (y & 1u));
+}
+
+/* ---------------------------------------------------------------------- */
+/* One Kawasaki attempt with the centre at (x, y).                          */
+/* ---------------------------------------------------------------------- */
+static uint32_t wrap_add(uint32_t v, int d, uint32_t L)
+{
+    if (d > 0)
+        return (v + 1u == L) ? 0u : v + 1u;
+    return (v == 0u) ? L - 1u : v - 1u;
+}
+
+static void partner_of(uint32_t x, uint32_t y, uint32_t dir, uint32_t L, uint32_t *bx, uint32_t *by)
+{
+    *bx = x;
+    *by = y;
+    if (dir == 0u)
+        *bx = wrap_add(x, +1, L);
+    else if (dir == 1u)
+        *bx = wrap_add(x, -1, L);
+    else if (dir == 2u)
+        *by = wrap_add(y, +1, L);
+    else
+        *by = wrap_add(y, -1, L);
+}
+
+/* Number of the 4 neighbours of (x, y), other than (ox, oy), whose type  */
+/* differs from `type`.                                                    */
+static int unlike_nbrs_except(const uint8_t *s, uint32_t L, uint32_t x, uint32_t y, uint32_t ox,
+                              uint32_t oy, uint8_t type)
+{
+    uint32_t nx[4], ny[4];
+    int q, count = 0;
+    nx[0] = wrap_add(x, +1, L); ny[0] = y;
+    nx[1] = wrap_add(x, -1, L); ny[1] = y;
+    nx[2] = x; ny[2] = wrap_add(y, +1, L);
+    nx[3] = x; ny[3] = wrap_add(y, -1, L);
+    for (q = 0; q < 4; ++q) {
+        if (nx[q] == ox && ny[q] == oy)
+            continue;
+        if (s[(size_t)ny[q] * L + nx[q]] != type)
+            ++count;
+    }
+    return count;
+}
+
+/* Change in N_AB if the pair (x,y)-(x,y)+dir were exchanged.  Only defined
+ * for an unlike pair: dU = (3 - n_c - n_c) + (3 - n_b - n_b) = 6 - 2n. */
+int ko_local_dnab(const uint8_t *s, uint32_t L, uint32_t x, uint32_t y, uint32_t dir)
+{
+    uint32_t bx, by;
+    uint8_t sc, sb;
+    int nc, nb;
+    partner_of(x, y, dir, L, &bx, &by);
+    sc = s[(size_t)y * L + x];
+    sb = s[(size_t)by * L + bx];
+    if (sc == sb)
+        return 0;
+    nc = unlike_nbrs_except(s, L, x, y, bx, by, sc);
+    nb = unlike_nbrs_except(s, L, bx, by, x, y, sb);
+    return 6 - 2 * (nc + nb);
+}
+
+static int attempt(uint8_t *s, uint32_t L, uint32_t x, uint32_t y, uint16_t rr, const uint64_t T[7],
+                   uint64_t seed, uint64_t t)
+{
+    uint32_t dir = (uint32_t)rr >> 10, u10 = (uint32_t)rr & 0x3FFu;
+    uint32_t bx, by;
+    uint8_t sc, sb;
+    int n;
+    uint64_t thr;
+    int accept;
+    partner_of(x, y, dir, L, &bx, &by);
+    sc = s[(size_t)y * L + x];
+    sb = s[(size_t)by * L + bx];
+    if (sc == sb)
+        return 0; /* exchanging like lipids changes nothing */
+    n = unlike_nbrs_except(s, L, x, y, bx, by, sc) + unlike_nbrs_except(s, L, bx, by, x, y, sb);
+    thr = T[n];
+    /* U = u10 * 2^32 + ext32 < thr.  The prefix decides unless it equals   */
+    /* thr's top bits; only then is the low word needed.                    */
+    if ((uint64_t)u10 != (thr >> 32))
+        accept = (uint64_t)u10 < (thr >> 32);
+    else
+        accept = (uint64_t)ko_ext_word(seed, t, x, y) < (thr & 0xFFFFFFFFull);
+    if (accept) {
+        s[(size_t)y * L + x] = sb;
+        s[(size_t)by * L + bx] = sc;
+        return 1;
+    }
+    return 0;
+}
+
+static uint64_t fnv1a(const uint8_t *s, size_t n)
+{
+    uint64_t h = 1469598103934665603ull;
+    size_t i;
+    for (i = 0; i < n; ++i) {
+        h ^= s[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t ko_lattice_hash(const uint8_t *s, uint32_t L)
+{
+    return fnv1a(s, (size_t)L * L);
+}
+
+/* ---------------------------------------------------------------------- */
+/* n_sweeps sweeps starting at sweep counter t0.  Returns the number of     */
+/* accepted exchanges.  Optional per-sweep lattice hashes locate the first  */
+/* divergence in a failed comparison.  Within one class the attempts are    */
+/* independent, so the row loop may run on several threads.                 */
+/* ---------------------------------------------------------------------- */
+uint64_t ko_sweeps(uint8_t *s, uint32_t L, double omega, uint64_t seed, uint64_t t0, uint64_t n_sweeps,
+                   uint64_t *hash_trace)
+{
+    uint64_t T[7], accepted = 0, i;
+    uint16_t *r = (uint16_t *)malloc((size_t)L * L * sizeof(uint16_t));
+    if (!r)
+        return ~(uint64_t)0;
+    ko_thresholds(omega, T);
+    for (i = 0; i < n_sweeps; ++i) {
+        uint64_t t = t0 + i;
+        int perm[8], p;
+        ko_sweep_randoms(L, seed, t, r);
+        ko_phase_order(seed, t, perm);
+        for (p = 0; p < 8; ++p) {
+            uint32_t a = (uint32_t)perm[p] >> 1, b = (uint32_t)perm[p] & 1u;
+            long yy;
+            uint64_t acc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : acc)
+            for (yy = (long)b; yy < (long)L; yy += 2) {
+                uint32_t y = (uint32_t)yy, x;
+                for (x = (a + y) & 3u; x < L; x += 4u)
+                    acc += (uint64_t)attempt(s, L, x, y, r[(size_t)y * L + x], T, seed, t);
+            }
+            accepted += acc;
+        }
+        if (hash_trace)
+            hash_trace[i] = fnv1a(s, (size_t)L * L);
+    }
+    free(r);
+    return accepted;
+}
+
+/* ---------------------------------------------------------------------- */
+/* N_AB: number of nearest-neighbour bonds joining unlike lipids (2N bonds */
+/* on the periodic square lattice).  E/kT = omega * N_AB.                  */
+/* ---------------------------------------------------------------------- */
+uint64_t ko_energy(const uint8_t *s, uint32_t L)
+{
+    uint64_t nab = 0;
+    uint32_t x, y;
+    for (y = 0; y < L; ++y)
+        for (x = 0; x < L; ++x) {
+            uint8_t v = s[(size_t)y * L + x];
+            nab += (v != s[(size_t)y * L + wrap_add(x, +1, L)]);
+            nab += (v != s[(size_t)wrap_add(y, +1, L) * L + x]);
+        }
+    return nab;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Initial placement: every site draws a 64-bit key from Philox block       */
+/* (y, x, 0, TAG_INIT<<28), key = word0 * 2^32 + word1; sites are sorted by */
+/* (key, y*L + x) and the first n1 = floor(c*N + 0.5) become type 1.  This  */
+/* is a uniformly random subset of exactly n1 sites.                        */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    uint64_t key;
+    uint64_t idx;
+} ko_keyed;
+
+static int cmp_keyed(const void *a, const void *b)
+{
+    const ko_keyed *p = (const ko_keyed *)a, *q = (const ko_keyed *)b;
+    if (p->key != q->key)
+        return p->key < q->key ? -1 : 1;
+    if (p->idx != q->idx)
+        return p->idx < q->idx ? -1 : 1;
+    return 0;
+}
+
+uint64_t ko_n_ones(uint32_t L, double composition)
+{
+    double N = (double)L * (double)L;
+    double v = floor(composition * N + 0.5);
+    if (v < 0.0)
+        v = 0.0;
+    if (v > N)
+        v = N;
+    return (uint64_t)v;
+}
+
+uint64_t ko_init_key(uint64_t seed, uint32_t x, uint32_t y)
+{
+    uint32_t key[2], ctr[4], out[4];
+    seed_to_key(seed, key);
+    ctr[0] = y;
+    ctr[1] = x;
+    ctr[2] = 0;
+    ctr[3] = KO_TAG_INIT << 28;
+    ko_philox4x32_10(ctr, key, out);
+    return ((uint64_t)out[0] << 32) | (uint64_t)out[1];
+}
+
+int ko_init(uint8_t *s, uint32_t L, double composition, uint64_t seed)
+{
+    size_t N = (size_t)L * L, i;
+    uint64_t n1 = ko_n_ones(L, composition);
+    ko_keyed *ks = (ko_keyed *)malloc(N * sizeof(ko_keyed));
+    if (!ks)
+        return -1;
+    for (i = 0; i < N; ++i) {
+        ks[i].key = ko_init_key(seed, (uint32_t)(i % L), (uint32_t)(i / L));
+        ks[i].idx = i;
+    }
+    qsort(ks, N, sizeof(ko_keyed), cmp_keyed);
+    memset(s, 0, N);
+    for (i = 0; i < (size_t)n1; ++i)
+        s[ks[i].idx] = 1;
+    free(ks);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Cluster-size histogram: maximal 4-connected (periodic) sets of sites of */
+/* one species, found by breadth-first search.  counts[s] (s = 0..N) gets  */
+/* the number of clusters of exactly s sites.  Returns the cluster count.  */
+/* ---------------------------------------------------------------------- */
+uint64_t ko_cluster_counts(const uint8_t *s, uint32_t L, int species, uint64_t *counts)
+{
+    size_t N = (size_t)L * L, i;
+    uint8_t *seen = (uint8_t *)calloc(N, 1);
+    uint32_t *queue = (uint32_t *)malloc(N * sizeof(uint32_t));
+    uint64_t clusters = 0;
+    if (!seen || !queue) {
+        free(seen);
+        free(queue);
+        return ~(uint64_t)0;
+    }
+    memset(counts, 0, (N + 1) * sizeof(uint64_t));
+    for (i = 0; i < N; ++i) {
+        size_t head = 0, tail = 0;
+        if (seen[i] || s[i] != (uint8_t)species)
+            continue;
+        seen[i] = 1;
+        queue[tail++] = (uint32_t)i;
+        while (head < tail) {
+            uint32_t v = queue[head++], x = v % L, y = v / L, q;
+            uint32_t nb[4];
+            nb[0] = y * L + wrap_add(x, +1, L);
+            nb[1] = y * L + wrap_add(x, -1, L);
+            nb[2] = wrap_add(y, +1, L) * L + x;
+            nb[3] = wrap_add(y, -1, L) * L + x;
+            for (q = 0; q < 4; ++q)
+                if (!seen[nb[q]] && s[nb[q]] == (uint8_t)species) {
+                    seen[nb[q]] = 1;
+                    queue[tail++] = nb[q];
+                }
+        }
+        counts[tail] += 1;
+        ++clusters;
+    }
+    free(seen);
+    free(queue);
+    return clusters;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Classical sequential Kawasaki chain (the paper's CPU comparison method): */
+/* one step is N attempts, each at a uniformly random site with a uniformly */
+/* random neighbour, accepted with probability min(1, exp(-omega*dU)) drawn */
+/* from a 53-bit double.  It has its own generator (xoshiro256**, seeded by */
+/* splitmix64) and shares no random numbers with the contract above; it is */
+/* only compared statistically.                                             */
+/* ---------------------------------------------------------------------- */
+static uint64_t splitmix64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t rotl64(uint64_t v, int k)
+{
+    return (v << k) | (v >> (64 - k));
+}
+
+static uint64_t xoshiro_next(uint64_t st[4])
+{
+    uint64_t result = rotl64(st[1] * 5u, 7) * 9u;
+    uint64_t tt = st[1] << 17;
+    st[2] ^= st[0];
+    st[3] ^= st[1];
+    st[1] ^= st[2];
+    st[0] ^= st[3];
+    st[2] ^= tt;
+    st[3] = rotl64(st[3], 45);
+    return result;
+}
+
+static uint64_t below(uint64_t st[4], uint64_t n)
+{
+    /* unbiased draw in [0, n) by rejection */
+    uint64_t lim = (~(uint64_t)0) - ((~(uint64_t)0) % n);
+    uint64_t v;
+    do {
+        v = xoshiro_next(st);
+    } while (v >= lim);
+    return v % n;
+}
+
+/* Unlike bonds incident to (x,y) or (bx,by); the bond between the two is
+ * counted twice, which cancels in a before/after difference. */
+static int local_unlike_bonds(const uint8_t *s, uint32_t L, uint32_t x, uint32_t y, uint32_t bx, uint32_t by)
+{
+    uint32_t px[2], py[2];
+    int k, total = 0;
+    px[0] = x; py[0] = y;
+    px[1] = bx; py[1] = by;
+    for (k = 0; k < 2; ++k) {
+        uint8_t v = s[(size_t)py[k] * L + px[k]];
+        total += v != s[(size_t)py[k] * L + wrap_add(px[k], +1, L)];
+        total += v != s[(size_t)py[k] * L + wrap_add(px[k], -1, L)];
+        total += v != s[(size_t)wrap_add(py[k], +1, L) * L + px[k]];
+        total += v != s[(size_t)wrap_add(py[k], -1, L) * L + px[k]];
+    }
+    return total;
+}
+
+uint64_t ko_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_seed, uint64_t n_steps)
+{
+    uint64_t st[4], sm = rng_seed, accepted = 0, step, a;
+    uint64_t N = (uint64_t)L * L;
+    int k;
+    for (k = 0; k < 4; ++k)
+        st[k] = splitmix64_next(&sm);
+    for (step = 0; step < n_steps; ++step) {
+        for (a = 0; a < N; ++a) {
+            uint64_t site = below(st, N);
+            uint32_t x = (uint32_t)(site % L), y = (uint32_t)(site / L);
+            uint32_t dir = (uint32_t)below(st, 4), bx, by;
+            double u = (double)(xoshiro_next(st) >> 11) * (1.0 / 9007199254740992.0);
+            uint8_t *pc, *pb, tmp;
+            int before, dU;
+            partner_of(x, y, dir, L, &bx, &by);
+            pc = &s[(size_t)y * L + x];
+            pb = &s[(size_t)by * L + bx];
+            if (*pc == *pb)
+                continue;
+            /* energy change by recount: swap, count, and undo if rejected */
+            before = local_unlike_bonds(s, L, x, y, bx, by);
+            tmp = *pc; *pc = *pb; *pb = tmp;
+            dU = local_unlike_bonds(s, L, x, y, bx, by) - before;
+            if (u < exp(-omega * (double)dU)) {
+                ++accepted;
+            } else {
+                tmp = *pc; *pc = *pb; *pb = tmp;
+            }
+        }
+    }
+    return accepted;
+}

@@ -1,0 +1,446 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: published Philox known-answer vectors, a full energy recount, brute
+force over the class schedule, exact Boltzmann enumeration on 4x4, the
+random-mixing closed form at omega = 0, Onsager's nearest-neighbour
+correlation at 50:50, an independent sequential Kawasaki chain, scipy's
+connected-component labelling, and an independent pure-Python sweep that
+visits each class's centres in a shuffled order.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1309_4349_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+# --------------------------------------------------------------------------
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(tok, 16) for tok in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers(orc):
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert list(orc.philox4x32_10(ctr, key)) == want
+
+
+# --------------------------------------------------------------------------
+# Acceptance thresholds
+# --------------------------------------------------------------------------
+def test_thresholds_omega_zero_accepts_everything(orc):
+    assert all(int(v) == 1 << 42 for v in orc.thresholds(0.0))
+
+
+def test_thresholds_powers_of_two(orc):
+    # omega = ln(2)/2: exp(-omega * dU) = 2^(-dU/2), so dU = 6, 4, 2 give
+    # 2^-3, 2^-2, 2^-1 exactly (up to the rounding of ln 2 in double).
+    T = orc.thresholds(math.log(2.0) / 2.0)
+    for n, expo in ((0, 39), (1, 40), (2, 41)):
+        assert abs(int(T[n]) - (1 << expo)) <= 1
+    assert all(int(v) == 1 << 42 for v in T[3:])
+
+
+def test_thresholds_sign_symmetry_and_order(orc):
+    for w in (0.2, 0.5, 0.88, 1.4, 3.0):
+        Tp, Tm = orc.thresholds(w), orc.thresholds(-w)
+        for n in range(7):
+            assert Tp[n] == Tm[6 - n]          # p(omega, dU) = p(-omega, -dU)
+        assert all(Tp[n] <= Tp[n + 1] for n in range(6))   # fewer unlike neighbours: harder
+        assert int(Tp[3]) == 1 << 42          # dU = 0 always accepted
+    # a huge omega drives the uphill probabilities to zero
+    T = orc.thresholds(1e4)
+    assert int(T[0]) == 0 and int(T[6]) == 1 << 42
+
+
+# --------------------------------------------------------------------------
+# Local energy change against a full recount
+# --------------------------------------------------------------------------
+def _nab_numpy(s):
+    return int(np.count_nonzero(s != np.roll(s, -1, axis=1)) + np.count_nonzero(s != np.roll(s, -1, axis=0)))
+
+
+@pytest.mark.parametrize("L", [4, 8, 12, 20])
+def test_local_dnab_matches_full_recount(orc, L):
+    rng = np.random.default_rng(L)
+    for trial in range(300):
+        s = wl.random_lattice(L, rng.uniform(0.1, 0.9), int(rng.integers(1 << 30)))
+        x, y, d = int(rng.integers(L)), int(rng.integers(L)), int(rng.integers(4))
+        bx, by = x, y
+        if d == 0:
+            bx = (x + 1) % L
+        elif d == 1:
+            bx = (x - 1) % L
+        elif d == 2:
+            by = (y + 1) % L
+        else:
+            by = (y - 1) % L
+        got = orc.local_dnab(s, x, y, d)
+        if s[y, x] == s[by, bx]:
+            assert got == 0
+            continue
+        before = _nab_numpy(s)
+        t = s.copy()
+        t[y, x], t[by, bx] = s[by, bx], s[y, x]
+        assert got == _nab_numpy(t) - before
+
+
+def test_energy_matches_numpy(orc):
+    rng = np.random.default_rng(5)
+    for L in (4, 8, 36, 64, 100):
+        for _ in range(5):
+            s = wl.random_lattice(L, rng.uniform(0, 1), int(rng.integers(1 << 30)))
+            assert orc.energy(s) == _nab_numpy(s)
+    # special cases: uniform lattice has no unlike bonds, checkerboard has all 2N
+    L = 8
+    assert orc.energy(np.ones((L, L), np.uint8)) == 0
+    cb = (np.add.outer(np.arange(L), np.arange(L)) % 2).astype(np.uint8)
+    assert orc.energy(cb) == 2 * L * L
+
+
+# --------------------------------------------------------------------------
+# Class schedule: conflict-freedom by brute force
+# --------------------------------------------------------------------------
+def _nbrs(x, y, L):
+    return [((x + 1) % L, y), ((x - 1) % L, y), (x, (y + 1) % L), (x, (y - 1) % L)]
+
+
+@pytest.mark.parametrize("L", [4, 8, 12, 16])
+def test_classes_partition_and_conflict_free(orc, L):
+    cls = np.array([[orc.site_class(x, y) for x in range(L)] for y in range(L)])
+    counts = np.bincount(cls.ravel(), minlength=8)
+    assert list(counts) == [L * L // 8] * 8
+    for k in range(8):
+        centres = [(x, y) for y in range(L) for x in range(L) if cls[y, x] == k]
+        pairs = []
+        for c in centres:
+            for b in _nbrs(*c, L):
+                write = {c, b}
+                read = {c, b, *_nbrs(*c, L), *_nbrs(*b, L)}
+                pairs.append((c, write, read))
+        for c1, w1, _ in pairs:
+            for c2, _, r2 in pairs:
+                if c1 == c2:
+                    continue
+                assert not (w1 & r2), (L, k, c1, c2)
+
+
+# --------------------------------------------------------------------------
+# Phase order and random field: uniformity
+# --------------------------------------------------------------------------
+def test_phase_order_is_uniform_permutation(orc):
+    seen = np.zeros((8, 8))
+    for t in range(4000):
+        p = orc.phase_order(0xABCDEF, t)
+        assert sorted(p) == list(range(8))
+        for pos, k in enumerate(p):
+            seen[pos, k] += 1
+    expect = 4000 / 8
+    chi2 = ((seen - expect) ** 2 / expect).sum()
+    assert chi2 < 49 + 6 * math.sqrt(2 * 49)
+
+
+def test_sweep_random_field_uniform(orc):
+    r = orc.sweep_randoms(96, 77, 5).astype(np.int64)     # 96 = 3 segments per row
+    d = r >> 10
+    u = r & 0x3FF
+    dc = np.bincount(d.ravel(), minlength=4)
+    assert abs(dc - 96 * 96 / 4).max() < 5 * math.sqrt(96 * 96 / 4)
+    assert abs(u.mean() - 511.5) < 5 * 295.6 / 96
+    # a different sweep gives an unrelated field
+    r2 = orc.sweep_randoms(96, 77, 6).astype(np.int64)
+    assert (r2 == r).mean() < 0.01
+
+
+# --------------------------------------------------------------------------
+# An independent pure-Python sweep (shuffled order inside each class)
+# --------------------------------------------------------------------------
+def _python_sweep(orc, s, omega, seed, t, rng):
+    L = s.shape[0]
+    T = [int(v) for v in orc.thresholds(omega)]
+    r = orc.sweep_randoms(L, seed, t)
+    accepted = 0
+    for k in orc.phase_order(seed, t):
+        centres = [(x, y) for y in range(L) for x in range(L) if 2 * ((x - y) % 4) + (y % 2) == k]
+        rng.shuffle(centres)
+        for x, y in centres:
+            d, u10 = int(r[y, x]) >> 10, int(r[y, x]) & 0x3FF
+            bx, by = [((x + 1) % L, y), ((x - 1) % L, y), (x, (y + 1) % L), (x, (y - 1) % L)][d]
+            sc, sb = s[y, x], s[by, bx]
+            if sc == sb:
+                continue
+            n = sum(1 for q in _nbrs(x, y, L) if q != (bx, by) and s[q[1], q[0]] != sc)
+            n += sum(1 for q in _nbrs(bx, by, L) if q != (x, y) and s[q[1], q[0]] != sb)
+            U = (u10 << 32) | orc.ext_word(seed, t, x, y)
+            if U < T[n]:
+                s[y, x], s[by, bx] = sb, sc
+                accepted += 1
+    return accepted
+
+
+@pytest.mark.parametrize("L,omega", [(8, 0.5), (12, 1.2), (16, -0.7), (36, 0.88)])
+def test_oracle_sweep_matches_shuffled_python_sweep(orc, L, omega):
+    seed = 0x5EED0000 + L
+    a = orc.init(L, 0.4, seed)
+    b = a.copy()
+    rng = np.random.default_rng(L)
+    for t in range(4):
+        acc_c = orc.sweeps(a, omega, seed, t, 1)
+        acc_p = _python_sweep(orc, b, omega, seed, t, rng)
+        assert acc_c == acc_p
+        assert np.array_equal(a, b)
+
+
+def test_extension_word_decides_ties(orc):
+    # Force the tie branch: pick omega so that one threshold's top bits equal
+    # a site's prefix, and check the decision against the 42-bit comparison.
+    L, seed, t = 8, 99, 3
+    r = orc.sweep_randoms(L, seed, t)
+    u10 = int(r[0, 0]) & 0x3FF
+    ext = orc.ext_word(seed, t, 0, 0)
+    U = (u10 << 32) | ext
+    assert U >> 32 == u10 and U & 0xFFFFFFFF == ext
+    # the tag separates the streams: ext differs from the sweep-field block word
+    assert ext != orc.philox4x32_10([0, 0, t, 1 << 28], [seed, 0])[0]
+
+
+# --------------------------------------------------------------------------
+# Composition conservation, initial placement
+# --------------------------------------------------------------------------
+def test_composition_conserved(orc):
+    for L, x, w in ((8, 0.5, 0.5), (40, 0.3, 1.2), (64, 0.71, -0.4)):
+        s = orc.init(L, x, 1234)
+        n1 = int(s.sum())
+        assert n1 == orc.n_ones(L, x) == int(math.floor(x * L * L + 0.5))
+        for t in range(0, 50, 10):
+            orc.sweeps(s, w, 1234, t, 10)
+            assert int(s.sum()) == n1
+
+
+def test_init_edge_compositions(orc):
+    assert orc.init(8, 0.0, 1).sum() == 0
+    assert orc.init(8, 1.0, 1).sum() == 64
+    assert orc.init(8, 0.5 / 64, 1).sum() == 1   # floor(0.5 + 0.5) = 1
+
+
+def test_init_is_uniform_random_subset(orc):
+    L, x = 8, 0.25
+    n1 = orc.n_ones(L, x)
+    freq = np.zeros((L, L))
+    nab = []
+    for seed in range(3000):
+        s = orc.init(L, x, seed)
+        freq += s
+        nab.append(orc.energy(s))
+    N = L * L
+    p = n1 / N
+    sd = math.sqrt(3000 * p * (1 - p))
+    assert np.abs(freq - 3000 * p).max() < 5 * sd
+    # expected unlike bonds of a uniformly random subset: 2N * 2 n1 n0 / (N (N-1))
+    exact = 2 * N * 2 * n1 * (N - n1) / (N * (N - 1))
+    assert abs(np.mean(nab) - exact) < 5 * np.std(nab) / math.sqrt(len(nab))
+
+
+# --------------------------------------------------------------------------
+# Stationarity: exact Boltzmann distribution on 4x4
+# --------------------------------------------------------------------------
+def _batch_means_z(samples, target, nbatch=40):
+    b = np.array_split(np.asarray(samples, dtype=float), nbatch)
+    m = np.array([v.mean() for v in b])
+    return (m.mean() - target) / (m.std(ddof=1) / math.sqrt(nbatch))
+
+
+def test_4x4_degeneracies_by_enumeration(orc):
+    states = orc.enumerate_states(4, 8).reshape(-1, 4, 4)
+    nab = np.array([_nab_numpy(s) for s in states])
+    got = dict(zip(*np.unique(nab, return_counts=True)))
+    want = {}
+    with open(os.path.join(GOLDEN, "boltzmann_4x4_degeneracy.txt")) as f:
+        for line in f:
+            if not line.startswith("#") and line.strip():
+                a, b = line.split()
+                want[int(a)] = int(b)
+    assert {int(k): int(v) for k, v in got.items()} == want
+
+
+@pytest.mark.parametrize("omega", [0.5, 1.2])
+def test_4x4_chain_samples_boltzmann(orc, omega):
+    states = orc.enumerate_states(4, 8).reshape(-1, 4, 4)
+    nab = np.array([_nab_numpy(s) for s in states])
+    index = {orc.lattice_hash(np.ascontiguousarray(s)): i for i, s in enumerate(states)}
+    assert len(index) == len(states)
+    w = np.exp(-omega * (nab - nab.min()))
+    pstate = w / w.sum()
+    levels = np.unique(nab)
+    plevel = np.array([pstate[nab == m].sum() for m in levels])
+
+    s = orc.init(4, 0.5, 4242)
+    nsweep = 400_000
+    _, hashes = orc.sweeps(s, omega, 4242, 0, nsweep, trace=True)
+    idx = np.array([index[int(h)] for h in hashes[1000:]])
+    samples = nab[idx]
+    # mean N_AB
+    exact_mean = float((pstate * nab).sum())
+    assert abs(_batch_means_z(samples, exact_mean)) < 4.5
+    # every N_AB level's frequency
+    for m, p in zip(levels, plevel):
+        hits = int((samples == m).sum())
+        if p * len(samples) < 200:      # too rare for batch means: a Poisson bound on the count
+            lam = p * len(samples)
+            assert hits <= lam + 6 * math.sqrt(lam) + 6, (m, p, hits)
+            continue
+        z = _batch_means_z((samples == m).astype(float), p)
+        assert abs(z) < 5.0, (m, p)
+    # state-level chi-square on thinned samples (every 10th sweep)
+    thin = idx[::10]
+    counts = np.bincount(thin, minlength=len(states))
+    expect = pstate * len(thin)
+    chi2 = float(((counts - expect) ** 2 / expect).sum())
+    dof = len(states) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof), chi2
+
+
+# --------------------------------------------------------------------------
+# omega = 0: random mixing closed form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,x", [(32, 0.5), (48, 0.3)])
+def test_omega_zero_random_mixing(orc, L, x):
+    s = wl.segregated_lattice(L, x)          # far from equilibrium on purpose
+    orc.sweeps(s, 0.0, 11, 0, 300)
+    vals = []
+    for t in range(300, 6300):
+        orc.sweeps(s, 0.0, 11, t, 1)
+        vals.append(orc.energy(s))
+    N = L * L
+    n1 = int(s.sum())
+    exact = 2 * N * 2 * n1 * (N - n1) / (N * (N - 1))
+    assert abs(_batch_means_z(vals, exact)) < 4.5
+
+
+# --------------------------------------------------------------------------
+# 50:50 equilibrium against Onsager (lattice gas <-> Ising with J = omega/2)
+# --------------------------------------------------------------------------
+def _onsager_fab(omega):
+    from scipy.special import ellipk
+    K = omega / 2.0
+    k = 2 * math.sinh(2 * K) / math.cosh(2 * K) ** 2
+    ss = 0.5 / math.tanh(2 * K) * (1 + (2 / math.pi) * (2 * math.tanh(2 * K) ** 2 - 1) * ellipk(k * k))
+    return (1 - ss) / 2
+
+
+@pytest.mark.parametrize("omega", [0.3, 0.5])
+def test_half_half_matches_onsager(orc, omega):
+    L = 64
+    s = orc.init(L, 0.5, 7)
+    orc.sweeps(s, omega, 7, 0, 500)
+    f = []
+    for t in range(500, 6500):
+        orc.sweeps(s, omega, 7, t, 1)
+        f.append(orc.energy(s) / (2 * L * L))
+    target = _onsager_fab(omega)
+    b = np.array([v.mean() for v in np.array_split(np.array(f), 40)])
+    se = b.std(ddof=1) / math.sqrt(40)
+    # fixed composition and a finite torus shift <s s> by O(1/N); allow 1e-3 on top of 5 sigma
+    assert abs(b.mean() - target) < 5 * se + 1e-3, (b.mean(), target, se)
+
+
+# --------------------------------------------------------------------------
+# Agreement with the classical sequential random-site Kawasaki chain
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("x,omega", [(0.5, 0.6), (0.3, 0.9)])
+def test_equilibrium_matches_sequential_kawasaki(orc, x, omega):
+    L = 32
+    a = orc.init(L, x, 21)
+    b = a.copy()
+    orc.sweeps(a, omega, 21, 0, 1000)
+    orc.seq_kawasaki(b, omega, 22, 1000)
+    fa, fb = [], []
+    for t in range(1000, 9000):
+        orc.sweeps(a, omega, 21, t, 1)
+        orc.seq_kawasaki(b, omega, 1_000_003 * t, 1)
+        fa.append(orc.energy(a))
+        fb.append(orc.energy(b))
+
+    def bm(v):
+        m = np.array([q.mean() for q in np.array_split(np.array(v, float), 40)])
+        return m.mean(), m.std(ddof=1) / math.sqrt(40)
+
+    (ma, sa), (mb, sb) = bm(fa), bm(fb)
+    assert abs(ma - mb) < 5 * math.hypot(sa, sb), (ma, mb, sa, sb)
+
+
+# --------------------------------------------------------------------------
+# Cluster histogram against scipy labelling with a periodic merge
+# --------------------------------------------------------------------------
+def _scipy_periodic_hist(s, species):
+    from scipy import ndimage
+    L = s.shape[0]
+    mask = s == species
+    lab, n = ndimage.label(mask, structure=[[0, 1, 0], [1, 1, 1], [0, 1, 0]])
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    def union(a, b):
+        if a and b:
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[max(ra, rb)] = min(ra, rb)
+
+    for i in range(L):
+        union(lab[i, 0], lab[i, L - 1])
+        union(lab[0, i], lab[L - 1, i])
+    sizes = {}
+    for v in lab.ravel():
+        if v:
+            r = find(int(v))
+            sizes[r] = sizes.get(r, 0) + 1
+    hist = {}
+    for v in sizes.values():
+        hist[v] = hist.get(v, 0) + 1
+    return sorted(hist.items())
+
+
+@pytest.mark.parametrize("L", [4, 8, 33, 64, 100])
+def test_cluster_hist_matches_scipy(orc, L):
+    rng = np.random.default_rng(L)
+    for trial in range(6):
+        s = wl.random_lattice(L, rng.uniform(0.2, 0.8), int(rng.integers(1 << 30)))
+        for sp in (0, 1):
+            got = orc.cluster_hist(s, sp)
+            assert got == _scipy_periodic_hist(s, sp)
+            assert sum(k * c for k, c in got) == int((s == sp).sum())
+
+
+def test_cluster_hist_special_cases(orc):
+    L = 12
+    assert orc.cluster_hist(np.ones((L, L), np.uint8), 1) == [(L * L, 1)]
+    assert orc.cluster_hist(np.ones((L, L), np.uint8), 0) == []
+    cb = (np.add.outer(np.arange(L), np.arange(L)) % 2).astype(np.uint8)
+    assert orc.cluster_hist(cb, 1) == [(1, L * L // 2)]
+    stripes = np.zeros((L, L), np.uint8)
+    stripes[::2, :] = 1
+    assert orc.cluster_hist(stripes, 1) == [(L, L // 2)]     # each row wraps into one cluster
+    # a cluster that only connects through both wraps
+    s = np.zeros((L, L), np.uint8)
+    s[0, 0] = s[0, L - 1] = s[L - 1, 0] = s[L - 1, L - 1] = 1
+    assert orc.cluster_hist(s, 1) == [(4, 1)]
