@@ -1,0 +1,150 @@
+/*
+ * kk.h -- C ABI of libkk: Metropolis-Kawasaki exchange sweeps of a binary
+ * lipid mixture on a periodic square lattice, run on one AMD Instinct
+ * MI355X (gfx950) with hand-written HIP kernels.
+ *
+ * The method is the one of Lis & Pintal, "GPU-Based Massive Parallel
+ * Kawasaki Kinetics in Monte Carlo Modelling of Lipid Microdomains":
+ *  - lipids of type A (0) and B (1) fill the lattice; a move exchanges two
+ *    nearest neighbours (Kawasaki kinetics), so the composition never changes
+ *    (Materials and Methods, "Monte Carlo model with Kawasaki based kinetics");
+ *  - the only parameter is omega_AB = g_AB - (g_AA + g_BB)/2 in units of kT,
+ *    and a move that changes the number of unlike contacts N_AB by dU is
+ *    accepted with the Metropolis probability min(1, exp(-omega * dU))
+ *    (same section, the Metropolis criterion and the omega_AB equation);
+ *  - a sweep ("step") decomposes the lattice into disjoint domains many times
+ *    and lets every domain centre try one exchange at once, N attempts per
+ *    sweep in total (section "Massive Parallel Kawasaki Kinetics");
+ *  - cluster sizes of one species are the analysed observable (section
+ *    "Cluster Analysis methods").
+ * The square-lattice decomposition (8 conflict-free centre classes in a
+ * random order per sweep), the Philox4x32-10 random-number layout and the
+ * 42-bit acceptance threshold make every result bit-reproducible and
+ * independent of how the GPU tiles the lattice.
+ *
+ * Conventions for every call:
+ *  - Lattices cross the boundary as host arrays of L*L bytes, row-major
+ *    (index y*L + x), each 0 or 1.  The caller owns every host buffer; the
+ *    library never keeps a pointer to one after the call returns.
+ *  - A kk_sim owns all of its device memory and (unless one is supplied) its
+ *    own HIP stream on the device that was current at creation.
+ *  - Calls block until their GPU work is done, except kk_sweep_async.
+ *  - A handle is not thread-safe: use one handle per thread.
+ *  - Errors return a kk_status; kk_last_error() gives this thread's message.
+ *    After KK_EDEVICE the handle is poisoned and later calls return
+ *    KK_ESTATE (destroy it).
+ */
+#ifndef KK_H
+#define KK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kk_sim kk_sim;
+
+typedef enum {
+    KK_OK = 0,
+    KK_EINVAL = 1,  /* bad argument (NULL, out of range, wrong size) */
+    KK_ENOMEM = 2,  /* device or host allocation failed */
+    KK_EDEVICE = 3, /* a HIP call failed; the handle is poisoned */
+    KK_ESTATE = 4,  /* the handle was poisoned by an earlier device error */
+    KK_ETRUNC = 5   /* output capacity too small; *n_out holds the size needed */
+} kk_status;
+
+enum {
+    KK_LAYOUT_AUTO = 0,     /* bit-packed when L % 32 == 0, else int8 */
+    KK_LAYOUT_INT8 = 1,     /* device lattice: one byte (0/1) per site */
+    KK_LAYOUT_BITPACKED = 2 /* device lattice: one bit per site, L/32 uint32 per row; needs L % 32 == 0 */
+};
+
+typedef struct {
+    uint64_t size;  /* cluster size in sites */
+    uint64_t count; /* number of clusters of that size */
+} kk_hist_entry;
+
+/* Create a simulation: an L x L periodic lattice with n1 = floor(composition*L*L + 0.5)
+ * sites of type 1 placed uniformly at random from `seed` (the paper's random start,
+ * Results, "MPKK vs. Kawasaki method"), interaction omega_kT (any finite value;
+ * positive favours demixing), sweep counter t = 0.
+ * L must be a multiple of 4 in [4, 32768] (a multiple of 32 for the bit-packed layout);
+ * composition must lie in [0, 1].  *out receives the handle (NULL on failure). */
+kk_status kk_create(kk_sim **out, uint32_t L, double composition, double omega_kT, uint64_t seed);
+
+/* kk_create with an explicit device layout (KK_LAYOUT_*) and an optional HIP
+ * stream (hipStream_t passed as void*; NULL = the handle creates its own).
+ * A supplied stream must outlive the handle. */
+kk_status kk_create_ex(kk_sim **out, uint32_t L, double composition, double omega_kT, uint64_t seed,
+                       uint32_t layout, void *hip_stream);
+
+/* Run n_sweeps sweeps (N attempts each, the paper's MPKK step), t .. t+n-1,
+ * and wait for them.  Advances the sweep counter. */
+kk_status kk_sweep(kk_sim *h, uint64_t n_sweeps);
+
+/* Enqueue n_sweeps sweeps on the handle's stream and return without waiting.
+ * Host-side counters advance immediately; kk_sync waits for the GPU. */
+kk_status kk_sweep_async(kk_sim *h, uint64_t n_sweeps);
+kk_status kk_sync(kk_sim *h);
+
+/* N_AB (unlike nearest-neighbour bonds over the 2N bonds of the torus) and
+ * E/kT = omega * N_AB (the Almeida model, Materials and Methods).  Either
+ * output pointer may be NULL. */
+kk_status kk_energy(kk_sim *h, uint64_t *n_unlike, double *energy_kT);
+
+/* Cluster-size histogram of `species` (0 or 1): maximal 4-connected periodic
+ * sets of sites of that type (the Hoshen-Kopelman analysis of "Cluster
+ * Analysis methods", here on the square torus).  Writes up to `cap`
+ * (size, count) pairs in ascending size to `out` and the number of distinct
+ * sizes to *n_out.  Returns KK_ETRUNC (with *n_out set) when cap is too
+ * small; `out` may be NULL when cap == 0. */
+kk_status kk_cluster_hist(kk_sim *h, int species, kk_hist_entry *out, size_t cap, size_t *n_out);
+
+/* Copy the lattice to host_out (n must be L*L bytes, values 0/1). */
+kk_status kk_get_lattice(kk_sim *h, uint8_t *host_out, size_t n);
+
+/* Replace the lattice with host_in (n == L*L bytes, each 0 or 1) and set the
+ * sweep counter to sweep_t: together with kk_get_lattice this is an exact
+ * checkpoint/resume, since every random number is addressed by (seed, t, site). */
+kk_status kk_set_lattice(kk_sim *h, const uint8_t *host_in, size_t n, uint64_t sweep_t);
+
+/* Sweeps done (= the sweep counter t), attempts made (t' * L * L over the sweeps
+ * run by this handle) and exchanges accepted.  NULL outputs are skipped. */
+kk_status kk_stats(kk_sim *h, uint64_t *sweeps, uint64_t *attempts, uint64_t *accepted);
+
+/* The 7 acceptance thresholds T[n] = min(2^42, ceil(exp(-omega*(6-2n)) * 2^42)),
+ * n = number of unlike neighbours of the pair excluding each other. */
+kk_status kk_thresholds(kk_sim *h, uint64_t out[7]);
+
+/* Side length and device layout (KK_LAYOUT_INT8 or KK_LAYOUT_BITPACKED). */
+kk_status kk_info(kk_sim *h, uint32_t *L, uint32_t *layout);
+
+/* Override the sweep tile: tile_words x 32 sites wide, tile_rows rows high
+ * (even), units_per_thread 1 or 2; tile_words == 0 selects the single cyclic
+ * tile holding the whole lattice (needs L % 32 == 0 and at most 1536 row-pair
+ * words, (L/2)*(L/32) <= 1536).  Results do not depend on the tile (the decomposition is
+ * conflict-free); only speed does. */
+kk_status kk_set_tile(kk_sim *h, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread);
+kk_status kk_get_tile(kk_sim *h, uint32_t *tile_words, uint32_t *tile_rows, uint32_t *units_per_thread);
+
+/* The handle's HIP stream (hipStream_t as void*) for callers that order or time
+ * their own work against it. */
+kk_status kk_stream(kk_sim *h, void **stream_out);
+
+/* Run n_sweeps sweeps recording a HIP event pair around every sweep-kernel
+ * launch; *kernel_ms receives the summed kernel time and *launches the number
+ * of sweep-kernel launches.  For profiling; results equal kk_sweep's. */
+kk_status kk_sweep_timed(kk_sim *h, uint64_t n_sweeps, double *kernel_ms, uint64_t *launches);
+
+void kk_destroy(kk_sim *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *kk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KK_H */

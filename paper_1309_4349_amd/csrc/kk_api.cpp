@@ -1,0 +1,617 @@
+// kk_api.cpp -- host side of libkk: the C ABI declared in include/kk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/kk.h"
+#include "kk_host.hpp"
+#include "kk_kernels.hpp"
+
+namespace kk {
+
+thread_local std::string g_last_error;
+
+kk_status set_error(kk_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void acceptance_table(double omega, uint64_t T[7], Accept* acc) {
+  const double two42 = 4398046511104.0;
+  for (int n = 0; n <= 6; ++n) {
+    const double p = std::exp(-omega * (6.0 - 2.0 * n));
+    const double v = std::ceil(p * two42);
+    T[n] = (v < two42) ? (uint64_t)v : (uint64_t)1 << 42;
+  }
+  std::memset(acc, 0, sizeof *acc);
+  if (omega == 0.0) return;  // every unlike exchange is accepted
+  acc->restricted = 0xFFFFFFFFu;
+  acc->negmask = omega < 0.0 ? 0xFFFFFFFFu : 0u;
+  // slot j covers m & 3 == j + 1 with m = n + 1: n = j (omega > 0) or n = 4 + j (omega < 0)
+  for (int j = 0; j < 3; ++j) {
+    const uint64_t v = T[omega > 0.0 ? j : 4 + j];
+    acc->hi[j] = (uint32_t)(v >> 32);  // 1024 when the move is always accepted
+    acc->lo[j] = (uint32_t)(v & 0xFFFFFFFFu);
+  }
+}
+
+int max_threads(int ku) { return ku == 1 ? 1024 : 768; }
+
+bool cyclic_fits(int L) {
+  return (L % 32) == 0 && (size_t)(L / 2) * (size_t)(L / 32) <= (size_t)2 * max_threads(2);
+}
+
+void default_tile(int L, int layout, TileConfig* tc) {
+  (void)layout;
+  if (cyclic_fits(L)) {
+    tc->cyclic = true;
+    tc->tww = L / 32;
+    tc->th = L;
+    const int units = (L / 2) * (L / 32);
+    tc->ku = units > max_threads(1) ? 2 : 1;
+    return;
+  }
+  static const int cand[][2] = {{8, 256}, {8, 128}, {4, 128}, {4, 64}, {2, 64}, {2, 32}};
+  const int ncand = (int)(sizeof cand / sizeof cand[0]);
+  int pick = ncand - 1;
+  for (int i = 0; i < ncand; ++i) {
+    const int tww = std::min(cand[i][0], (L + 31) / 32);
+    const int th = std::min(cand[i][1], L);
+    const long tiles = (long)((L + 32 * tww - 1) / (32 * tww)) * ((L + th - 1) / th);
+    if (tiles >= 128) {
+      pick = i;
+      break;
+    }
+  }
+  tc->cyclic = false;
+  tc->tww = std::min(cand[pick][0], (L + 31) / 32);
+  tc->th = std::min(cand[pick][1], L);
+  tc->ku = 2;
+}
+
+// Fill the geometry fields of p for lattice side L and tile config tc.
+// Returns the workgroup size.
+int tile_geometry(int L, const TileConfig& tc, SweepParams* p) {
+  p->L = L;
+  p->wpr = L / 32;
+  p->tww = tc.tww;
+  p->th = tc.th;
+  if (tc.cyclic) {
+    p->hx = 0;
+    p->hy = 0;
+    p->tiles_x = 1;
+    p->C = L / 32;
+    p->R = L;
+    p->row0 = 0;
+    p->npairs = L / 2;
+  } else {
+    p->hx = 1;
+    p->hy = 16;
+    p->tiles_x = (L + 32 * tc.tww - 1) / (32 * tc.tww);
+    p->C = tc.tww + 2;
+    p->R = tc.th + 32;
+    p->row0 = 2;
+    p->npairs = (p->R - 4) / 2;
+  }
+  p->nunits = p->npairs * p->C;
+  const int per = (p->nunits + tc.ku - 1) / tc.ku;
+  return ((per + 63) / 64) * 64;
+}
+
+bool tile_valid(int L, const TileConfig& tc, std::string* why) {
+  if (tc.ku != 1 && tc.ku != 2) { *why = "units_per_thread must be 1 or 2"; return false; }
+  if (tc.cyclic) {
+    if (!cyclic_fits(L)) { *why = "cyclic tile needs L % 32 == 0 and (L/2)*(L/32) <= 1536"; return false; }
+  } else {
+    if (tc.tww < 1 || tc.th < 2 || (tc.th & 1)) { *why = "tile_words >= 1 and an even tile_rows >= 2 needed"; return false; }
+  }
+  SweepParams p{};
+  const int threads = tile_geometry(L, tc, &p);
+  if (threads > max_threads(tc.ku)) { *why = "tile needs more threads than a workgroup allows"; return false; }
+  const size_t lds = (size_t)p.R * (p.C + 2) * 4;
+  if (lds > 160 * 1024) { *why = "tile does not fit in 160 KiB of LDS"; return false; }
+  return true;
+}
+
+}  // namespace kk
+
+using namespace kk;
+
+struct kk_sim {
+  int L = 0;
+  int layout = 0;
+  double composition = 0, omega = 0;
+  uint64_t seed = 0;
+  uint32_t k0 = 0, k1 = 0;
+  uint64_t t = 0;
+  uint64_t attempts = 0;
+  void* lat[2] = {nullptr, nullptr};
+  int cur = 0;
+  unsigned long long* counters = nullptr;  // [0] accepted, [1] energy scratch
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  uint64_t T[7] = {};
+  Accept acc{};
+  TileConfig tile{};
+  CclBuffers ccl{};
+  bool ccl_ready = false;
+  bool poisoned = false;
+};
+
+namespace {
+
+#define KK_HIP(expr)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) {                                                                              \
+      if (h) h->poisoned = true;                                                                         \
+      return set_error(KK_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
+                       __LINE__);                                                                        \
+    }                                                                                                    \
+  } while (0)
+
+#define KK_GUARD(hh)                                                                       \
+  do {                                                                                     \
+    if (!(hh)) return set_error(KK_EINVAL, "NULL handle");                                 \
+    if ((hh)->poisoned) return set_error(KK_ESTATE, "handle poisoned by an earlier error"); \
+  } while (0)
+
+size_t lattice_bytes(const kk_sim* h) {
+  return h->layout == kLayoutBits ? (size_t)h->L * (size_t)(h->L / 32) * 4 : (size_t)h->L * (size_t)h->L;
+}
+
+void free_all(kk_sim* h) {
+  for (int i = 0; i < 2; ++i)
+    if (h->lat[i]) (void)hipFree(h->lat[i]);
+  if (h->counters) (void)hipFree(h->counters);
+  if (h->ccl.parent) (void)hipFree(h->ccl.parent);
+  if (h->ccl.size) (void)hipFree(h->ccl.size);
+  if (h->ccl.hist) (void)hipFree(h->ccl.hist);
+  if (h->ccl.big) (void)hipFree(h->ccl.big);
+  if (h->ccl.big_count) (void)hipFree(h->ccl.big_count);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+kk_status dmalloc(kk_sim* h, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    (void)h;
+    return set_error(KK_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return KK_OK;
+}
+
+// Uniform random subset of exactly n1 sites: radix select of the n1-th
+// smallest Philox key, then ties (equal 64-bit keys) broken by site index.
+kk_status place_initial(kk_sim* h) {
+  const int L = h->L;
+  const size_t N = (size_t)L * L;
+  const uint64_t n1 = place_count(L, h->composition);
+  void* dst = h->lat[h->cur];
+  const size_t bytes = lattice_bytes(h);
+  if (n1 == 0) {
+    KK_HIP(hipMemsetAsync(dst, 0, bytes, h->stream));
+    KK_HIP(hipStreamSynchronize(h->stream));
+    return KK_OK;
+  }
+  if (n1 == N) {
+    KK_HIP(hipMemsetAsync(dst, h->layout == kLayoutBits ? 0xFF : 0x01, bytes, h->stream));
+    KK_HIP(hipStreamSynchronize(h->stream));
+    return KK_OK;
+  }
+  uint64_t* keys = nullptr;
+  unsigned* hist = nullptr;
+  kk_status st = dmalloc(h, (void**)&keys, N * sizeof(uint64_t));
+  if (st != KK_OK) return st;
+  const unsigned eq_cap = 4096;
+  st = dmalloc(h, (void**)&hist, (256 + 1 + eq_cap) * sizeof(unsigned));
+  if (st != KK_OK) {
+    (void)hipFree(keys);
+    return st;
+  }
+  unsigned* eq_count = hist + 256;
+  uint32_t* eq_list = reinterpret_cast<uint32_t*>(hist + 257);
+  auto fail = [&](const char* what, hipError_t e) {
+    (void)hipFree(keys);
+    (void)hipFree(hist);
+    h->poisoned = true;
+    return set_error(KK_EDEVICE, "%s failed: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e = launch_init_keys(keys, L, h->k0, h->k1, h->stream);
+  if (e != hipSuccess) return fail("init_keys", e);
+  uint64_t prefix = 0, need = n1;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    unsigned hh[256];
+    if ((e = hipMemsetAsync(hist, 0, 256 * sizeof(unsigned), h->stream)) != hipSuccess) return fail("memset", e);
+    if ((e = launch_radix_hist(keys, N, prefix, shift, hist, h->stream)) != hipSuccess) return fail("radix_hist", e);
+    if ((e = hipMemcpyAsync(hh, hist, sizeof hh, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+      return fail("copy hist", e);
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return fail("sync", e);
+    uint64_t cum = 0;
+    int d = 0;
+    for (; d < 256; ++d) {
+      if (cum + hh[d] >= need) break;
+      cum += hh[d];
+    }
+    prefix |= (uint64_t)d << shift;
+    need -= cum;
+  }
+  // sites with key < prefix are ones; `need` of the sites with key == prefix too
+  if ((e = hipMemsetAsync(eq_count, 0, sizeof(unsigned), h->stream)) != hipSuccess) return fail("memset", e);
+  if ((e = launch_init_mark(keys, L, h->layout, prefix, dst, eq_count, eq_list, eq_cap, h->stream)) != hipSuccess)
+    return fail("init_mark", e);
+  unsigned neq = 0;
+  if ((e = hipMemcpyAsync(&neq, eq_count, sizeof neq, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+    return fail("copy eq", e);
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return fail("sync", e);
+  if (neq > eq_cap || need > neq) {
+    (void)hipFree(keys);
+    (void)hipFree(hist);
+    return set_error(KK_EDEVICE, "initial placement: %u equal keys (cap %u), need %llu", neq, eq_cap,
+                     (unsigned long long)need);
+  }
+  std::vector<uint32_t> idx(neq);
+  if (neq) {
+    if ((e = hipMemcpyAsync(idx.data(), eq_list, neq * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream)) !=
+        hipSuccess)
+      return fail("copy eq list", e);
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return fail("sync", e);
+    std::sort(idx.begin(), idx.end());
+    idx.resize((size_t)need);
+    if ((e = hipMemcpyAsync(eq_list, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                            h->stream)) != hipSuccess)
+      return fail("upload ties", e);
+    if ((e = launch_set_sites(eq_list, (unsigned)idx.size(), L, h->layout, dst, h->stream)) != hipSuccess)
+      return fail("set_sites", e);
+  }
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return fail("sync", e);
+  (void)hipFree(keys);
+  (void)hipFree(hist);
+  return KK_OK;
+}
+
+// Launch sweeps [h->t, h->t + n) on the handle's stream.  With `timing`, an
+// event pair brackets every launch and the kernel time is accumulated.
+kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
+  SweepParams p{};
+  const int threads = tile_geometry(h->L, h->tile, &p);
+  p.accepted = h->counters;
+  p.k0 = h->k0;
+  p.k1 = h->k1;
+  p.acc = h->acc;
+  const uint64_t per_launch = h->tile.cyclic ? 256 : 1;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (kernel_ms) {
+    KK_HIP(hipEventCreate(&ev[0]));
+    KK_HIP(hipEventCreate(&ev[1]));
+    *kernel_ms = 0.0;
+  }
+  uint64_t nl = 0;
+  while (n > 0) {
+    const uint64_t k = n < per_launch ? n : per_launch;
+    p.src = h->lat[h->cur];
+    p.dst = h->lat[h->cur ^ 1];
+    p.t0 = h->t;
+    p.nsweeps = (int)k;
+    if (kernel_ms) KK_HIP(hipEventRecord(ev[0], h->stream));
+    KK_HIP(launch_sweep(p, h->layout, h->tile.cyclic, h->tile.ku, threads, h->stream));
+    if (kernel_ms) {
+      KK_HIP(hipEventRecord(ev[1], h->stream));
+      KK_HIP(hipEventSynchronize(ev[1]));
+      float ms = 0.f;
+      KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      *kernel_ms += ms;
+    }
+    h->cur ^= 1;
+    h->t += k;
+    h->attempts += k * (uint64_t)h->L * (uint64_t)h->L;
+    n -= k;
+    ++nl;
+  }
+  if (kernel_ms) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
+  if (launches) *launches = nl;
+  return KK_OK;
+}
+
+}  // namespace
+
+namespace kk {
+uint64_t place_count(int L, double composition) {
+  const double N = (double)L * (double)L;
+  double v = std::floor(composition * N + 0.5);
+  if (v < 0.0) v = 0.0;
+  if (v > N) v = N;
+  return (uint64_t)v;
+}
+}  // namespace kk
+
+extern "C" {
+
+const char* kk_last_error(void) { return g_last_error.c_str(); }
+
+kk_status kk_create(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed) {
+  return kk_create_ex(out, L, composition, omega_kT, seed, KK_LAYOUT_AUTO, nullptr);
+}
+
+kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed,
+                       uint32_t layout, void* hip_stream) {
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 4 || (L % 4) != 0 || L > 32768)
+    return set_error(KK_EINVAL, "L must be a multiple of 4 in [4, 32768] (got %u)", L);
+  if (!(composition >= 0.0 && composition <= 1.0))
+    return set_error(KK_EINVAL, "composition must lie in [0, 1]");
+  if (!std::isfinite(omega_kT)) return set_error(KK_EINVAL, "omega must be finite");
+  int lay;
+  if (layout == KK_LAYOUT_AUTO) lay = (L % 32 == 0) ? kLayoutBits : kLayoutInt8;
+  else if (layout == KK_LAYOUT_INT8) lay = kLayoutInt8;
+  else if (layout == KK_LAYOUT_BITPACKED) {
+    if (L % 32 != 0) return set_error(KK_EINVAL, "bit-packed layout needs L %% 32 == 0 (got %u)", L);
+    lay = kLayoutBits;
+  } else return set_error(KK_EINVAL, "unknown layout %u", layout);
+
+  kk_sim* h = new (std::nothrow) kk_sim();
+  if (!h) return set_error(KK_ENOMEM, "host allocation failed");
+  h->L = (int)L;
+  h->layout = lay;
+  h->composition = composition;
+  h->omega = omega_kT;
+  h->seed = seed;
+  h->k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  h->k1 = (uint32_t)(seed >> 32);
+  acceptance_table(omega_kT, h->T, &h->acc);
+  default_tile(h->L, lay, &h->tile);
+  kk_status st = KK_OK;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return set_error(KK_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+  }
+  if (hip_stream) h->stream = static_cast<hipStream_t>(hip_stream);
+  else {
+    e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete h;
+      return set_error(KK_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    h->own_stream = true;
+  }
+  const size_t bytes = lattice_bytes(h);
+  for (int i = 0; i < 2 && st == KK_OK; ++i) st = dmalloc(h, &h->lat[i], bytes);
+  if (st == KK_OK) st = dmalloc(h, (void**)&h->counters, 2 * sizeof(unsigned long long));
+  if (st == KK_OK) {
+    e = hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned long long), h->stream);
+    if (e != hipSuccess) st = set_error(KK_EDEVICE, "memset failed: %s", hipGetErrorString(e));
+  }
+  if (st == KK_OK) st = place_initial(h);
+  if (st != KK_OK) {
+    free_all(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return KK_OK;
+}
+
+kk_status kk_sweep_async(kk_sim* h, uint64_t n) {
+  KK_GUARD(h);
+  return enqueue_sweeps(h, n, nullptr, nullptr);
+}
+
+kk_status kk_sync(kk_sim* h) {
+  KK_GUARD(h);
+  KK_HIP(hipStreamSynchronize(h->stream));
+  return KK_OK;
+}
+
+kk_status kk_sweep(kk_sim* h, uint64_t n) {
+  KK_GUARD(h);
+  kk_status st = enqueue_sweeps(h, n, nullptr, nullptr);
+  if (st != KK_OK) return st;
+  KK_HIP(hipStreamSynchronize(h->stream));
+  return KK_OK;
+}
+
+kk_status kk_sweep_timed(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
+  KK_GUARD(h);
+  double ms = 0.0;
+  uint64_t nl = 0;
+  kk_status st = enqueue_sweeps(h, n, &ms, &nl);
+  if (st != KK_OK) return st;
+  KK_HIP(hipStreamSynchronize(h->stream));
+  if (kernel_ms) *kernel_ms = ms;
+  if (launches) *launches = nl;
+  return KK_OK;
+}
+
+kk_status kk_energy(kk_sim* h, uint64_t* n_unlike, double* energy_kT) {
+  KK_GUARD(h);
+  KK_HIP(hipMemsetAsync(h->counters + 1, 0, sizeof(unsigned long long), h->stream));
+  KK_HIP(launch_energy(h->lat[h->cur], h->layout, h->L, h->counters + 1, h->stream));
+  unsigned long long v = 0;
+  KK_HIP(hipMemcpyAsync(&v, h->counters + 1, sizeof v, hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  if (n_unlike) *n_unlike = v;
+  if (energy_kT) *energy_kT = h->omega * (double)v;
+  return KK_OK;
+}
+
+kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap, size_t* n_out) {
+  KK_GUARD(h);
+  if (species != 0 && species != 1) return set_error(KK_EINVAL, "species must be 0 or 1");
+  if (!n_out) return set_error(KK_EINVAL, "n_out is NULL");
+  if (cap > 0 && !out) return set_error(KK_EINVAL, "out is NULL with cap > 0");
+  const size_t N = (size_t)h->L * h->L;
+  if (!h->ccl_ready) {
+    kk_status st = dmalloc(h, (void**)&h->ccl.parent, N * 4);
+    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.size, N * 4);
+    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.hist, kSmallSizes * 4);
+    h->ccl.big_cap = (unsigned)(N / kSmallSizes + 1);
+    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.big, (size_t)h->ccl.big_cap * 4);
+    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.big_count, 4);
+    if (st != KK_OK) return st;
+    h->ccl_ready = true;
+  }
+  KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
+  KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
+  KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
+  KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->stream));
+  std::vector<unsigned> hs(kSmallSizes);
+  unsigned nbig = 0;
+  KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipMemcpyAsync(&nbig, h->ccl.big_count, 4, hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  if (nbig > h->ccl.big_cap) return set_error(KK_EDEVICE, "cluster list overflow (%u > %u)", nbig, h->ccl.big_cap);
+  std::vector<uint32_t> big(nbig);
+  if (nbig) {
+    KK_HIP(hipMemcpyAsync(big.data(), h->ccl.big, nbig * 4, hipMemcpyDeviceToHost, h->stream));
+    KK_HIP(hipStreamSynchronize(h->stream));
+  }
+  std::map<uint64_t, uint64_t> bigh;
+  for (uint32_t s : big) bigh[s] += 1;
+  size_t n = 0;
+  for (int s = 1; s < kSmallSizes; ++s) n += hs[s] != 0;
+  n += bigh.size();
+  *n_out = n;
+  if (cap < n) return set_error(KK_ETRUNC, "histogram has %zu entries, cap %zu", n, cap);
+  size_t i = 0;
+  for (int s = 1; s < kSmallSizes; ++s)
+    if (hs[s]) out[i++] = kk_hist_entry{(uint64_t)s, (uint64_t)hs[s]};
+  for (auto& kv : bigh) out[i++] = kk_hist_entry{kv.first, kv.second};
+  return KK_OK;
+}
+
+kk_status kk_get_lattice(kk_sim* h, uint8_t* host_out, size_t n) {
+  KK_GUARD(h);
+  const size_t N = (size_t)h->L * h->L;
+  if (!host_out || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*L = %zu bytes", N);
+  if (h->layout == kLayoutInt8) {
+    KK_HIP(hipMemcpyAsync(host_out, h->lat[h->cur], N, hipMemcpyDeviceToHost, h->stream));
+    KK_HIP(hipStreamSynchronize(h->stream));
+    return KK_OK;
+  }
+  uint8_t* tmp = nullptr;
+  kk_status st = dmalloc(h, (void**)&tmp, N);
+  if (st != KK_OK) return st;
+  hipError_t e = launch_unpack(static_cast<const uint32_t*>(h->lat[h->cur]), tmp, h->L, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_out, tmp, N, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return set_error(KK_EDEVICE, "get_lattice: %s", hipGetErrorString(e));
+  }
+  return KK_OK;
+}
+
+kk_status kk_set_lattice(kk_sim* h, const uint8_t* host_in, size_t n, uint64_t sweep_t) {
+  KK_GUARD(h);
+  const size_t N = (size_t)h->L * h->L;
+  if (!host_in || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*L = %zu bytes", N);
+  for (size_t i = 0; i < N; ++i)
+    if (host_in[i] > 1) return set_error(KK_EINVAL, "site %zu holds %u; sites must be 0 or 1", i, host_in[i]);
+  if (sweep_t >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "sweep counter must be < 2^60");
+  if (h->layout == kLayoutInt8) {
+    KK_HIP(hipMemcpyAsync(h->lat[h->cur], host_in, N, hipMemcpyHostToDevice, h->stream));
+  } else {
+    uint8_t* tmp = nullptr;
+    kk_status st = dmalloc(h, (void**)&tmp, N);
+    if (st != KK_OK) return st;
+    hipError_t e = hipMemcpyAsync(tmp, host_in, N, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_pack(tmp, static_cast<uint32_t*>(h->lat[h->cur]), h->L, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+      h->poisoned = true;
+      return set_error(KK_EDEVICE, "set_lattice: %s", hipGetErrorString(e));
+    }
+  }
+  KK_HIP(hipStreamSynchronize(h->stream));
+  h->t = sweep_t;
+  return KK_OK;
+}
+
+kk_status kk_stats(kk_sim* h, uint64_t* sweeps, uint64_t* attempts, uint64_t* accepted) {
+  KK_GUARD(h);
+  unsigned long long acc = 0;
+  KK_HIP(hipMemcpyAsync(&acc, h->counters, sizeof acc, hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  if (sweeps) *sweeps = h->t;
+  if (attempts) *attempts = h->attempts;
+  if (accepted) *accepted = acc;
+  return KK_OK;
+}
+
+kk_status kk_thresholds(kk_sim* h, uint64_t out[7]) {
+  KK_GUARD(h);
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  for (int i = 0; i < 7; ++i) out[i] = h->T[i];
+  return KK_OK;
+}
+
+kk_status kk_info(kk_sim* h, uint32_t* L, uint32_t* layout) {
+  KK_GUARD(h);
+  if (L) *L = (uint32_t)h->L;
+  if (layout) *layout = h->layout == kLayoutBits ? KK_LAYOUT_BITPACKED : KK_LAYOUT_INT8;
+  return KK_OK;
+}
+
+kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread) {
+  KK_GUARD(h);
+  TileConfig tc{};
+  tc.ku = (int)units_per_thread;
+  if (tile_words == 0) {
+    tc.cyclic = true;
+    tc.tww = h->L / 32;
+    tc.th = h->L;
+  } else {
+    tc.cyclic = false;
+    tc.tww = (int)tile_words;
+    tc.th = (int)tile_rows;
+  }
+  std::string why;
+  if (!tile_valid(h->L, tc, &why)) return set_error(KK_EINVAL, "invalid tile: %s", why.c_str());
+  h->tile = tc;
+  return KK_OK;
+}
+
+kk_status kk_get_tile(kk_sim* h, uint32_t* tile_words, uint32_t* tile_rows, uint32_t* units_per_thread) {
+  KK_GUARD(h);
+  if (tile_words) *tile_words = h->tile.cyclic ? 0u : (uint32_t)h->tile.tww;
+  if (tile_rows) *tile_rows = (uint32_t)h->tile.th;
+  if (units_per_thread) *units_per_thread = (uint32_t)h->tile.ku;
+  return KK_OK;
+}
+
+kk_status kk_stream(kk_sim* h, void** stream_out) {
+  KK_GUARD(h);
+  if (!stream_out) return set_error(KK_EINVAL, "stream_out is NULL");
+  *stream_out = h->stream;
+  return KK_OK;
+}
+
+void kk_destroy(kk_sim* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+}  // extern "C"

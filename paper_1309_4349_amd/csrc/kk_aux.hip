@@ -1,0 +1,289 @@
+// kk_aux.hip -- initial placement, energy, cluster labelling and layout
+// conversion kernels of libkk.
+#include "kk_common.hpp"
+#include "kk_kernels.hpp"
+
+namespace kk {
+
+namespace {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int site_bit(const void* lat, int layout, int L, int x, int y) {
+  if (layout == kLayoutBits)
+    return (int)((static_cast<const uint32_t*>(lat)[(size_t)y * (L >> 5) + (x >> 5)] >> (x & 31)) & 1u);
+  return (int)(static_cast<const uint8_t*>(lat)[(size_t)y * L + x] & 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Energy: N_AB = sum over sites of [s(x,y) != s(x+1,y)] + [s(x,y) != s(x,y+1)]
+// (the Almeida one-parameter model, E/kT = omega * N_AB + const).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void energy_bits(const uint32_t* lat, int L, unsigned long long* out) {
+  const int wpr = L >> 5;
+  const size_t nw = (size_t)L * wpr;
+  unsigned long long acc = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / wpr), g = (int)(i - (size_t)y * wpr);
+    const uint32_t v = lat[i];
+    const uint32_t nxt = lat[(size_t)y * wpr + (g + 1 == wpr ? 0 : g + 1)];
+    const uint32_t east = __builtin_amdgcn_alignbit(nxt, v, 1);
+    const uint32_t below = lat[(size_t)(y + 1 == L ? 0 : y + 1) * wpr + g];
+    acc += (unsigned)__builtin_popcount(v ^ east) + (unsigned)__builtin_popcount(v ^ below);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
+__global__ __launch_bounds__(256) void energy_int8(const uint8_t* lat, int L, unsigned long long* out) {
+  const size_t n = (size_t)L * L;
+  unsigned long long acc = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
+    const uint8_t v = lat[i];
+    acc += (v != lat[(size_t)y * L + (x + 1 == L ? 0 : x + 1)]);
+    acc += (v != lat[(size_t)(y + 1 == L ? 0 : y + 1) * L + x]);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Initial placement: each site's 64-bit key is Philox block (y, x, 0, tag 4)
+// words 0 and 1; the n1 sites with the smallest (key, index) get type 1.
+// The n1-th smallest key is found by an 8-pass MSB-first radix select.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1) {
+  const size_t n = (size_t)L * L;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i - (size_t)y * L);
+    const Philox4 r = philox10(y, x, 0u, kTagInit << 28, k0, k1);
+    keys[i] = ((uint64_t)r.x << 32) | (uint64_t)r.y;
+  }
+}
+
+__global__ __launch_bounds__(256) void radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, int shift,
+                                                  unsigned* hist) {
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int hs = shift + 8;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    if (hs >= 64 || (k >> hs) == (prefix >> hs)) atomicAdd(&h[(k >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat,
+                                                 unsigned* eq_count, uint32_t* eq_list, unsigned eq_cap) {
+  if (layout == kLayoutBits) {
+    const int wpr = L >> 5;
+    const size_t nw = (size_t)L * wpr;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+      uint32_t v = 0;
+      const size_t base = i * 32;  // words tile rows exactly, so site index = 32 * word + bit
+      for (int b = 0; b < 32; ++b) {
+        const uint64_t k = keys[base + b];
+        if (k < kth) v |= 1u << b;
+        else if (k == kth) {
+          const unsigned slot = atomicAdd(eq_count, 1u);
+          if (slot < eq_cap) eq_list[slot] = (uint32_t)(base + b);
+        }
+      }
+      static_cast<uint32_t*>(lat)[i] = v;
+    }
+  } else {
+    const size_t n = (size_t)L * L;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+      const uint64_t k = keys[i];
+      uint8_t v = 0;
+      if (k < kth) v = 1;
+      else if (k == kth) {
+        const unsigned slot = atomicAdd(eq_count, 1u);
+        if (slot < eq_cap) eq_list[slot] = (uint32_t)i;
+      }
+      static_cast<uint8_t*>(lat)[i] = v;
+    }
+  }
+}
+
+__global__ void set_sites(const uint32_t* idx, unsigned n, int L, int layout, void* lat) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = idx[i];
+  if (layout == kLayoutBits) atomicOr(&static_cast<uint32_t*>(lat)[s >> 5], 1u << (s & 31u));
+  else static_cast<uint8_t*>(lat)[s] = 1;
+  (void)L;
+}
+
+// ---------------------------------------------------------------------------
+// Cluster labelling: lock-free union-find with atomicMin on parent links
+// (parents always point to smaller indices, so no cycle can form), then
+// path flattening, per-root site counts and a size histogram.  Small sizes
+// go to a dense histogram through a per-block LDS copy; the few sizes of
+// kSmallSizes or more are appended to a list.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_parent(const uint32_t* parent, uint32_t x) {
+  return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t find_root(const uint32_t* parent, uint32_t x) {
+  uint32_t p = ld_parent(parent, x);
+  while (p != x) {
+    x = p;
+    p = ld_parent(parent, x);
+  }
+  return x;
+}
+
+__device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
+  for (;;) {
+    a = find_root(parent, a);
+    b = find_root(parent, b);
+    if (a == b) return;
+    if (a > b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint32_t old = atomicMin(&parent[b], a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int species, uint32_t* parent) {
+  const size_t n = (size_t)L * L;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
+    parent[i] = (site_bit(lat, layout, L, x, y) == species) ? (uint32_t)i : kNone;
+  }
+}
+
+__global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, int L, int species,
+                                                 uint32_t* parent) {
+  const size_t n = (size_t)L * L;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
+    if (site_bit(lat, layout, L, x, y) != species) continue;
+    const int xr = (x + 1 == L) ? 0 : x + 1, yd = (y + 1 == L) ? 0 : y + 1;
+    if (site_bit(lat, layout, L, xr, y) == species) unite(parent, (uint32_t)i, (uint32_t)((size_t)y * L + xr));
+    if (site_bit(lat, layout, L, x, yd) == species) unite(parent, (uint32_t)i, (uint32_t)((size_t)yd * L + x));
+  }
+}
+
+__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, uint32_t* size) {
+  const size_t n = (size_t)L * L;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    if (parent[i] == kNone) continue;
+    const uint32_t r = find_root(parent, (uint32_t)i);
+    atomicAdd(&size[r], 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, unsigned* hist, uint32_t* big,
+                                                unsigned* big_count, unsigned big_cap) {
+  __shared__ unsigned h[kSmallSizes];
+  for (int k = threadIdx.x; k < kSmallSizes; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  const size_t n = (size_t)L * L;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t s = size[i];
+    if (s == 0) continue;
+    if (s < (uint32_t)kSmallSizes) atomicAdd(&h[s], 1u);
+    else {
+      const unsigned slot = atomicAdd(big_count, 1u);
+      if (slot < big_cap) big[slot] = s;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kSmallSizes; k += blockDim.x)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pack_bits(const uint8_t* in, uint32_t* out, int L) {
+  const size_t nw = (size_t)L * (L >> 5);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) v |= (uint32_t)(in[i * 32 + b] & 1u) << b;
+    out[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void unpack_bits(const uint32_t* in, uint8_t* out, int L) {
+  const size_t nw = (size_t)L * (L >> 5);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t v = in[i];
+    for (int b = 0; b < 32; ++b) out[i * 32 + b] = (uint8_t)((v >> b) & 1u);
+  }
+}
+
+int grid_for(size_t n, int block) {
+  size_t g = (n + block - 1) / block;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_energy(const void* lat, int layout, int L, unsigned long long* out, hipStream_t stream) {
+  if (layout == kLayoutBits)
+    hipLaunchKernelGGL(energy_bits, dim3(grid_for((size_t)L * (L >> 5), 256)), dim3(256), 0, stream,
+                       static_cast<const uint32_t*>(lat), L, out);
+  else
+    hipLaunchKernelGGL(energy_int8, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream,
+                       static_cast<const uint8_t*>(lat), L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1, hipStream_t stream) {
+  hipLaunchKernelGGL(init_keys, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream, keys, L, k0, k1);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, int shift, unsigned* hist256,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(radix_hist, dim3(grid_for(n, 256)), dim3(256), 0, stream, keys, n, prefix, shift, hist256);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat, unsigned* eq_count,
+                            uint32_t* eq_list, unsigned eq_cap, hipStream_t stream) {
+  const size_t n = layout == kLayoutBits ? (size_t)L * (L >> 5) : (size_t)L * L;
+  hipLaunchKernelGGL(init_mark, dim3(grid_for(n, 256)), dim3(256), 0, stream, keys, L, layout, kth, lat, eq_count,
+                     eq_list, eq_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_sites(const uint32_t* idx, unsigned n, int L, int layout, void* lat, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(set_sites, dim3((n + 255) / 256), dim3(256), 0, stream, idx, n, L, layout, lat);
+  return hipGetLastError();
+}
+
+hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, hipStream_t stream) {
+  const size_t n = (size_t)L * L;
+  const int g = grid_for(n, 256);
+  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  hipLaunchKernelGGL(ccl_merge, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, b.size);
+  hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, b.hist, b.big,
+                     b.big_count, b.big_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stream) {
+  hipLaunchKernelGGL(pack_bits, dim3(grid_for((size_t)L * (L >> 5), 256)), dim3(256), 0, stream, in, out, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint32_t* in, uint8_t* out, int L, hipStream_t stream) {
+  hipLaunchKernelGGL(unpack_bits, dim3(grid_for((size_t)L * (L >> 5), 256)), dim3(256), 0, stream, in, out, L);
+  return hipGetLastError();
+}
+
+}  // namespace kk

@@ -1,0 +1,59 @@
+// kk_kernels.hpp -- launch parameter blocks and host-side launchers of the
+// libkk HIP kernels (internal to the library; the public API is kk.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kk_common.hpp"
+
+namespace kk {
+
+constexpr int kLayoutInt8 = 1;  // one byte (0/1) per site, row-major
+constexpr int kLayoutBits = 2;  // one bit per site, L/32 words per row, bit b of word g = site 32g + b
+
+struct SweepParams {
+  const void* src;
+  void* dst;
+  unsigned long long* accepted;
+  int L, wpr;                // side; words per row of the bit-packed layout
+  int tww, th;               // interior words / rows per tile
+  int hx, hy;                // halo words / rows on each side (1/16, or 0/0 for the cyclic tile)
+  int tiles_x;
+  int C, R;                  // LDS words per row, rows (tile + halo)
+  int row0, npairs, nunits;  // first computed LDS row, computed row pairs, units = pairs * C
+  int nsweeps;               // sweeps in this launch
+  uint32_t k0, k1;           // Philox key (seed)
+  uint64_t t0;               // first sweep index
+  Accept acc;
+};
+
+hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream);
+
+// N_AB (unlike nearest-neighbour bonds) added into *out.
+hipError_t launch_energy(const void* lat, int layout, int L, unsigned long long* out, hipStream_t stream);
+
+// Initial placement.
+hipError_t launch_init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1, hipStream_t stream);
+hipError_t launch_radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, int shift, unsigned* hist256,
+                             hipStream_t stream);
+hipError_t launch_init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat, unsigned* eq_count,
+                            uint32_t* eq_list, unsigned eq_cap, hipStream_t stream);
+hipError_t launch_set_sites(const uint32_t* idx, unsigned n, int L, int layout, void* lat, hipStream_t stream);
+
+// Connected components of one species (4-neighbour, periodic) and their size histogram.
+struct CclBuffers {
+  uint32_t* parent;     // N
+  uint32_t* size;       // N
+  unsigned* hist;       // small-size histogram, kSmallSizes entries
+  uint32_t* big;        // sizes >= kSmallSizes, appended
+  unsigned* big_count;  // number of appended sizes
+  unsigned big_cap;
+};
+constexpr int kSmallSizes = 4096;
+hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, hipStream_t stream);
+
+// int8 <-> bit-packed conversion on the device (bit-packed needs L % 32 == 0).
+hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stream);
+hipError_t launch_unpack(const uint32_t* in, uint8_t* out, int L, hipStream_t stream);
+
+}  // namespace kk

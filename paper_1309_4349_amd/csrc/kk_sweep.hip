@@ -1,0 +1,372 @@
+// kk_sweep.hip -- the Kawasaki sweep kernel (the hot loop).
+//
+// One launch performs complete sweeps (8 class phases each) on LDS-resident
+// tiles of the lattice, stored one bit per site.  Each 32-bit LDS word holds
+// 32 consecutive sites of a row; a phase touches every 4th bit of every
+// other row, and the 8 centres of a word are decided together with bitwise
+// (SWAR) logic against the word's 12 bit-sliced random planes.
+//
+// Two tile modes:
+//  * halo tiles (hx = 1 word, hy = 16 rows on each side): one sweep per
+//    launch.  A phase's dependency radius is 2 sites, so after 8 phases the
+//    interior is exact while the outermost 16 rows / 16 bits of the halo
+//    may be stale; the counter-based random numbers make the redundant halo
+//    work reproduce exactly what the neighbouring tile computes.
+//  * cyclic tile (whole lattice, L % 32 == 0): rows and words wrap inside
+//    LDS, so no halo exists and any number of sweeps runs in one launch.
+//
+// Within a phase all chosen pairs are at L1 distance >= 2 from one another
+// (classes 2*((x - y) mod 4) + (y mod 2)), so no pair writes a site that
+// another pair reads: the LDS updates are xor-flips of disjoint bits issued
+// with ds_xor, and a workgroup barrier separates phases.
+#include "kk_common.hpp"
+#include "kk_kernels.hpp"
+
+namespace kk {
+
+namespace {
+
+__device__ __forceinline__ uint32_t sel4(uint32_t d1, uint32_t d0, uint32_t v0, uint32_t v1, uint32_t v2,
+                                         uint32_t v3) {
+  // direction (d1 d0): 0 -> v0 (+x), 1 -> v1 (-x), 2 -> v2 (+y), 3 -> v3 (-y), per bit
+  const uint32_t lo = (d0 & v1) | (~d0 & v0);
+  const uint32_t hi = (d0 & v3) | (~d0 & v2);
+  return (d1 & hi) | (~d1 & lo);
+}
+
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+  return (a & b) | (a & c) | (b & c);
+}
+
+// Pack 32 bytes (each 0 or 1) into one word, byte b -> bit b.
+__device__ __forceinline__ uint32_t pack4(uint32_t d) {
+  return (d | (d >> 7) | (d >> 14) | (d >> 21)) & 0xFu;
+}
+
+// Spread 4 bits into 4 bytes (bit b -> byte b, value 0/1).
+__device__ __forceinline__ uint32_t spread4(uint32_t n) {
+  return (n * 0x00204081u) & 0x01010101u;
+}
+
+template <int LAYOUT>
+__device__ uint32_t load_word(const SweepParams& p, int yv, int Xw) {
+  const int L = p.L;
+  const int y = imod(yv, L);
+  if (LAYOUT == kLayoutBits) {
+    const int xw = imod(Xw, L);  // a multiple of 32: the bit-packed layout needs L % 32 == 0
+    return static_cast<const uint32_t*>(p.src)[(size_t)y * p.wpr + (xw >> 5)];
+  } else {
+    const uint8_t* row = static_cast<const uint8_t*>(p.src) + (size_t)y * L;
+    if (Xw >= 0 && Xw + 32 <= L) {
+      uint32_t v = 0;
+      if ((L & 15) == 0) {
+        const uint4* d = reinterpret_cast<const uint4*>(row + Xw);
+        const uint4 a = d[0], b = d[1];
+        v = pack4(a.x) | (pack4(a.y) << 4) | (pack4(a.z) << 8) | (pack4(a.w) << 12) | (pack4(b.x) << 16) |
+            (pack4(b.y) << 20) | (pack4(b.z) << 24) | (pack4(b.w) << 28);
+      } else {
+        const uint32_t* d = reinterpret_cast<const uint32_t*>(row + Xw);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v |= pack4(d[k]) << (4 * k);
+      }
+      return v;
+    }
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) v |= (uint32_t)(row[imod(Xw + b, L)] & 1u) << b;
+    return v;
+  }
+}
+
+// Store the low `nbits` sites of word v at true coordinates (x0, y).
+template <int LAYOUT>
+__device__ void store_word(const SweepParams& p, int y, int x0, uint32_t v, int nbits) {
+  if (LAYOUT == kLayoutBits) {
+    static_cast<uint32_t*>(p.dst)[(size_t)y * p.wpr + (x0 >> 5)] = v;
+  } else {
+    uint8_t* row = static_cast<uint8_t*>(p.dst) + (size_t)y * p.L;
+    if (nbits == 32) {
+      if ((p.L & 15) == 0) {
+        uint4* d = reinterpret_cast<uint4*>(row + x0);
+        d[0] = make_uint4(spread4(v & 0xFu), spread4((v >> 4) & 0xFu), spread4((v >> 8) & 0xFu),
+                          spread4((v >> 12) & 0xFu));
+        d[1] = make_uint4(spread4((v >> 16) & 0xFu), spread4((v >> 20) & 0xFu), spread4((v >> 24) & 0xFu),
+                          spread4(v >> 28));
+      } else {
+        uint32_t* d = reinterpret_cast<uint32_t*>(row + x0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[k] = spread4((v >> (4 * k)) & 0xFu);
+      }
+    } else {
+      for (int b = 0; b < nbits; ++b) row[x0 + b] = (uint8_t)((v >> b) & 1u);
+    }
+  }
+}
+
+// The 12 random planes of the 32 virtual sites starting at virtual x = Xw in
+// virtual row yv for sweep t.  Segment-aligned windows take the three Philox
+// blocks of their segment directly; windows that straddle the periodic wrap
+// of an L % 32 != 0 lattice (or L < 32) gather from the segments they cover.
+__device__ void gen_planes(const SweepParams& p, int yv, int Xw, uint64_t t, uint32_t* pl) {
+  const int L = p.L;
+  const uint32_t y = (uint32_t)imod(yv, L);
+  const uint32_t tl = (uint32_t)t, thi = ctr_hi(t, kTagSweep);
+  const int x0 = imod(Xw, L);
+  if ((x0 & 31) == 0 && x0 + 32 <= L) {
+    const uint32_t g4 = (uint32_t)(x0 >> 5) * 4u;
+    const Philox4 a = philox10(y, g4 + 0u, tl, thi, p.k0, p.k1);
+    const Philox4 b = philox10(y, g4 + 1u, tl, thi, p.k0, p.k1);
+    const Philox4 c = philox10(y, g4 + 2u, tl, thi, p.k0, p.k1);
+    pl[0] = a.x; pl[1] = a.y; pl[2] = a.z; pl[3] = a.w;
+    pl[4] = b.x; pl[5] = b.y; pl[6] = b.z; pl[7] = b.w;
+    pl[8] = c.x; pl[9] = c.y; pl[10] = c.z; pl[11] = c.w;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kPlanes; ++k) pl[k] = 0u;
+  int b = 0;
+  while (b < 32) {
+    const int x = imod(Xw + b, L);
+    const int off = x & 31;
+    int len = 32 - off;
+    if (L - x < len) len = L - x;
+    if (32 - b < len) len = 32 - b;
+    const uint32_t g4 = (uint32_t)(x >> 5) * 4u;
+    const Philox4 q0 = philox10(y, g4 + 0u, tl, thi, p.k0, p.k1);
+    const Philox4 q1 = philox10(y, g4 + 1u, tl, thi, p.k0, p.k1);
+    const Philox4 q2 = philox10(y, g4 + 2u, tl, thi, p.k0, p.k1);
+    const uint32_t P[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+    const uint32_t m = (len == 32) ? 0xFFFFFFFFu : ((1u << len) - 1u);
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k) pl[k] |= ((P[k] >> off) & m) << b;
+    b += len;
+  }
+}
+
+// 10-bit (u < K) and (u == K) over bit-sliced u, planes[2] = MSB .. planes[11] = LSB,
+// processed from the least significant bit: lt' = maj(~u_k, K_k, lt).
+__device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& lt, uint32_t& eq) {
+  uint32_t l = 0u, e = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    const uint32_t u = pl[11 - k];
+    const uint32_t kb = 0u - ((K >> k) & 1u);
+    l = maj3(~u, kb, l);
+    e = e & ~(u ^ kb);
+  }
+  lt = l;
+  eq = e;
+}
+
+template <bool CYC>
+__device__ __forceinline__ unsigned sweep_item(uint32_t* S, const SweepParams& p, int stride, int r, int w,
+                                               const uint32_t* pl, uint32_t cmask, uint32_t intmask, int yv,
+                                               int Xw, uint64_t t) {
+  int rn, rs, rnn, rss, wl, wr;
+  if (CYC) {
+    const int R = p.R, C = p.C;
+    rn = (r == 0) ? R - 1 : r - 1;
+    rs = (r + 1 == R) ? 0 : r + 1;
+    rnn = (rn == 0) ? R - 1 : rn - 1;
+    rss = (rs + 1 == R) ? 0 : rs + 1;
+    wl = (w == 0) ? C - 1 : w - 1;
+    wr = (w + 1 == C) ? 0 : w + 1;
+  } else {
+    rn = r - 1;
+    rs = r + 1;
+    rnn = r - 2;
+    rss = r + 2;
+    wl = w - 1;  // the pad words at -1 and C are never part of a result
+    wr = w + 1;
+  }
+#define KK_AT(rr, ww) S[(rr) * stride + (ww) + 1]
+  const uint32_t c0 = KK_AT(r, w), cL = KK_AT(r, wl), cR = KK_AT(r, wr);
+  const uint32_t n0 = KK_AT(rn, w), nL = KK_AT(rn, wl), nR = KK_AT(rn, wr);
+  const uint32_t s0 = KK_AT(rs, w), sL = KK_AT(rs, wl), sR = KK_AT(rs, wr);
+  const uint32_t nn = KK_AT(rnn, w), ss = KK_AT(rss, w);
+
+  // value of the site at x+1 / x-1 / x+2 / x-2, aligned to bit x
+  const uint32_t cE = __builtin_amdgcn_alignbit(cR, c0, 1);
+  const uint32_t cW = __builtin_amdgcn_alignbit(c0, cL, 31);
+  const uint32_t cE2 = __builtin_amdgcn_alignbit(cR, c0, 2);
+  const uint32_t cW2 = __builtin_amdgcn_alignbit(c0, cL, 30);
+  const uint32_t nE = __builtin_amdgcn_alignbit(nR, n0, 1);
+  const uint32_t nW = __builtin_amdgcn_alignbit(n0, nL, 31);
+  const uint32_t sE = __builtin_amdgcn_alignbit(sR, s0, 1);
+  const uint32_t sW = __builtin_amdgcn_alignbit(s0, sL, 31);
+
+  const uint32_t d0 = pl[0], d1 = pl[1];
+  // partner b: +x east, -x west, +y the row below (y+1), -y the row above
+  const uint32_t B = sel4(d1, d0, cE, cW, s0, n0);
+  const uint32_t A = (c0 ^ B) & cmask;  // centres of this class whose partner is unlike
+
+  // m = n + 1 = (unlike neighbours of c, partner included) + (neighbours of b
+  // other than c that equal c, i.e. are unlike b)
+  const uint32_t o1 = sel4(d1, d0, cE2, cW2, ss, nn);
+  const uint32_t o2 = sel4(d1, d0, nE, nW, sW, nW);
+  const uint32_t o3 = sel4(d1, d0, sE, sW, sE, nE);
+  const uint32_t uE = c0 ^ cE, uW = c0 ^ cW, uN = c0 ^ n0, uS = c0 ^ s0;
+  const uint32_t e1 = ~(c0 ^ o1), e2 = ~(c0 ^ o2), e3 = ~(c0 ^ o3);
+  const uint32_t s1 = uE ^ uW ^ uN, c1 = maj3(uE, uW, uN);
+  const uint32_t s2 = uS ^ e1 ^ e2, c2 = maj3(uS, e1, e2);
+  const uint32_t m0 = s1 ^ s2 ^ e3, c3 = maj3(s1, s2, e3);
+  const uint32_t m1 = c1 ^ c2 ^ c3, m2 = maj3(c1, c2, c3);
+
+  uint32_t F = A;  // accepted exchanges
+  if (p.acc.restricted) {
+    uint32_t lt0, eq0, lt1, eq1, lt2, eq2;
+    if (p.acc.hi[0] < 1024u) cmp10(pl, p.acc.hi[0], lt0, eq0); else { lt0 = 0xFFFFFFFFu; eq0 = 0u; }
+    if (p.acc.hi[1] < 1024u) cmp10(pl, p.acc.hi[1], lt1, eq1); else { lt1 = 0xFFFFFFFFu; eq1 = 0u; }
+    if (p.acc.hi[2] < 1024u) cmp10(pl, p.acc.hi[2], lt2, eq2); else { lt2 = 0xFFFFFFFFu; eq2 = 0u; }
+    const uint32_t rm = ~(m2 ^ p.acc.negmask) & (m0 | m1);  // m in the rejectable range
+    const uint32_t ltsel = (m1 & ((m0 & lt2) | (~m0 & lt1))) | (~m1 & lt0);
+    const uint32_t eqsel = (m1 & ((m0 & eq2) | (~m0 & eq1))) | (~m1 & eq0);
+    F = A & (~rm | ltsel);
+    uint32_t tie = A & rm & eqsel;
+    while (tie) {  // u10 equals the threshold prefix: draw the low 32 bits
+      const int bp = __builtin_ctz(tie);
+      tie &= tie - 1u;
+      const uint32_t x = (uint32_t)imod(Xw + bp, p.L), y = (uint32_t)imod(yv, p.L);
+      const Philox4 e = philox10(y, x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
+      const uint32_t xs = x & 3u;
+      const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
+      const uint32_t j = ((((m1 >> bp) & 1u) << 1) | ((m0 >> bp) & 1u)) - 1u;
+      const uint32_t lo = j == 0 ? p.acc.lo[0] : j == 1 ? p.acc.lo[1] : p.acc.lo[2];
+      if (ext < lo) F |= 1u << bp;
+    }
+  }
+
+  const uint32_t Fpx = F & ~d1 & ~d0, Fmx = F & ~d1 & d0;
+  const uint32_t Fpy = F & d1 & ~d0, Fmy = F & d1 & d0;
+  const uint32_t flip = F ^ (Fpx << 1) ^ (Fmx >> 1);
+  if (flip) atomicXor(&KK_AT(r, w), flip);
+  if (Fpx >> 31) atomicXor(&KK_AT(r, wr), 1u);
+  if (Fmx & 1u) atomicXor(&KK_AT(r, wl), 0x80000000u);
+  if (Fpy) atomicXor(&KK_AT(rs, w), Fpy);
+  if (Fmy) atomicXor(&KK_AT(rn, w), Fmy);
+#undef KK_AT
+  return (unsigned)__builtin_popcount(F & intmask);
+}
+
+template <int LAYOUT, bool CYC, int KU>
+__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void sweep_kernel(SweepParams p) {
+  extern __shared__ uint32_t S[];
+  const int stride = p.C + 2;
+  const int tile = blockIdx.x;
+  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+  const int X0 = tx * p.tww * 32, Y0 = ty * p.th;
+  const int XL = X0 - 32 * p.hx;  // virtual x of LDS word 0
+  const int YT = Y0 - p.hy;       // virtual y of LDS row 0
+  const int xend = min(X0 + p.tww * 32, p.L);  // interior is [X0, xend) x [Y0, yend)
+  const int yend = min(Y0 + p.th, p.L);
+
+  // stage the tile (with halo) into LDS, one bit per site
+  for (int i = threadIdx.x; i < p.R * stride; i += blockDim.x) {
+    const int r = i / stride, w = i - r * stride - 1;
+    S[i] = (w >= 0 && w < p.C) ? load_word<LAYOUT>(p, YT + r, XL + 32 * w) : 0u;
+  }
+
+  // units owned by this thread: (row pair q, word w); rows r0 = row0 + 2q and r0 + 1
+  int ur0[KU], uw[KU];
+  bool uok[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int u = threadIdx.x + k * blockDim.x;
+    uok[k] = u < p.nunits;
+    const int q = uok[k] ? u / p.C : 0;
+    uw[k] = uok[k] ? u - q * p.C : 0;
+    ur0[k] = p.row0 + 2 * q;
+  }
+  // interior bit masks of each owned word (for counting accepted moves)
+  uint32_t imask[KU][2];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int Xw = XL + 32 * uw[k];
+    uint32_t wm = 0u;
+    if (Xw + 32 <= X0 || Xw >= xend) wm = 0u;
+    else {
+      const int lo = max(Xw, X0), hi = min(Xw + 32, xend);
+      const int n = hi - lo, sh = lo - Xw;
+      wm = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << sh;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int yv = YT + ur0[k] + h;
+      imask[k][h] = (uok[k] && yv >= Y0 && yv < yend) ? wm : 0u;
+    }
+  }
+
+  unsigned count = 0;
+  for (int s = 0; s < p.nsweeps; ++s) {
+    const uint64_t t = p.t0 + (uint64_t)s;
+    uint32_t pl[KU][2][kPlanes];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      if (!uok[k]) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) gen_planes(p, YT + ur0[k] + h, XL + 32 * uw[k], t, pl[k][h]);
+    }
+    const uint32_t perm = class_order(p.k0, p.k1, t);
+    __syncthreads();  // staging (or the previous sweep) complete
+    for (int ph = 0; ph < 8; ++ph) {
+      const uint32_t cls = (perm >> (4 * ph)) & 0xFu;
+      const int a = (int)(cls >> 1);
+      // Every unit starts on an even virtual row (tiles start on even rows and
+      // the halo is even), so the active row of the pair is row r0 + (class
+      // parity): uniform over the workgroup, which keeps the plane arrays in
+      // registers.
+      if ((cls & 1u) == 0u) {
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          if (!uok[k]) continue;
+          const int yv = YT + ur0[k];
+          count += sweep_item<CYC>(S, p, stride, ur0[k], uw[k], pl[k][0], 0x11111111u << ((a + yv) & 3),
+                                   imask[k][0], yv, XL + 32 * uw[k], t);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          if (!uok[k]) continue;
+          const int yv = YT + ur0[k] + 1;
+          count += sweep_item<CYC>(S, p, stride, ur0[k] + 1, uw[k], pl[k][1], 0x11111111u << ((a + yv) & 3),
+                                   imask[k][1], yv, XL + 32 * uw[k], t);
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // write the interior back
+  const int iw = (xend - X0 + 31) / 32, ih = yend - Y0;
+  for (int i = threadIdx.x; i < iw * ih; i += blockDim.x) {
+    const int rr = i / iw, ww = i - rr * iw;
+    const int x0 = X0 + 32 * ww;
+    const int nb = min(32, xend - x0);
+    const uint32_t v = S[(p.hy + rr) * stride + p.hx + ww + 1];
+    store_word<LAYOUT>(p, Y0 + rr, x0, nb == 32 ? v : (v & ((1u << nb) - 1u)), nb);
+  }
+
+  // accepted-move count: wave reduction, one atomic per wave
+  unsigned long long c = count;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(p.accepted, c);
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream) {
+  const int tiles_y = (p.L + p.th - 1) / p.th;
+  const dim3 grid(p.tiles_x * tiles_y), block(threads);
+  const size_t lds = (size_t)p.R * (p.C + 2) * sizeof(uint32_t);
+#define KK_LAUNCH(LY, CY, KUV) hipLaunchKernelGGL((sweep_kernel<LY, CY, KUV>), grid, block, lds, stream, p)
+  if (layout == kLayoutBits) {
+    if (cyclic) { if (ku == 1) KK_LAUNCH(kLayoutBits, true, 1); else KK_LAUNCH(kLayoutBits, true, 2); }
+    else { if (ku == 1) KK_LAUNCH(kLayoutBits, false, 1); else KK_LAUNCH(kLayoutBits, false, 2); }
+  } else {
+    if (cyclic) { if (ku == 1) KK_LAUNCH(kLayoutInt8, true, 1); else KK_LAUNCH(kLayoutInt8, true, 2); }
+    else { if (ku == 1) KK_LAUNCH(kLayoutInt8, false, 1); else KK_LAUNCH(kLayoutInt8, false, 2); }
+  }
+#undef KK_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace kk

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libkk (include/kk.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libkk.so.  Loading fails loudly when the library has not been
+built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkk.so")
+
+KK_OK, KK_EINVAL, KK_ENOMEM, KK_EDEVICE, KK_ESTATE, KK_ETRUNC = range(6)
+LAYOUT_AUTO, LAYOUT_INT8, LAYOUT_BITPACKED = 0, 1, 2
+_LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPACKED}
+
+EXPORTS = [
+    "kk_create", "kk_create_ex", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
+    "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile",
+    "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
+]
+
+
+class KKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libkk status {status}: {msg}")
+        self.status = status
+
+
+class HistEntry(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint64), ("count", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libkk.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with __graft_entry__.build() "
+                                "or python paper_1309_4349_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, U32, U64, D, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "kk_create": [PP, U32, D, D, U64],
+        "kk_create_ex": [PP, U32, D, D, U64, U32, P],
+        "kk_sweep": [P, U64],
+        "kk_sweep_async": [P, U64],
+        "kk_sync": [P],
+        "kk_energy": [P, u64p, dp],
+        "kk_cluster_hist": [P, I, ctypes.POINTER(HistEntry), ctypes.c_size_t, szp],
+        "kk_get_lattice": [P, P, ctypes.c_size_t],
+        "kk_set_lattice": [P, P, ctypes.c_size_t, U64],
+        "kk_stats": [P, u64p, u64p, u64p],
+        "kk_thresholds": [P, u64p],
+        "kk_info": [P, u32p, u32p],
+        "kk_set_tile": [P, U32, U32, U32],
+        "kk_get_tile": [P, u32p, u32p, u32p],
+        "kk_stream": [P, PP],
+        "kk_sweep_timed": [P, U64, dp, u64p],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.kk_destroy.argtypes = [P]
+    lib.kk_destroy.restype = None
+    lib.kk_last_error.argtypes = []
+    lib.kk_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != KK_OK:
+        raise KKError(st, load().kk_last_error().decode(errors="replace"))
+
+
+class Sim:
+    """One lattice simulation owned by libkk (device memory and stream)."""
+
+    def __init__(self, L: int, composition: float, omega: float, seed: int, layout: str = "auto",
+                 stream: Optional[int] = None):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.kk_create_ex(ctypes.byref(h), L, float(composition), float(omega), seed & (2**64 - 1),
+                                _LAYOUTS[layout], ctypes.c_void_p(stream) if stream else None))
+        self._h = h
+        self.L = L
+        self.omega = float(omega)
+        self.seed = seed
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().kk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the path -------------------------------------------------------------
+    def sweep(self, n: int):
+        _check(load().kk_sweep(self._h, n))
+
+    def sweep_async(self, n: int):
+        _check(load().kk_sweep_async(self._h, n))
+
+    def sync(self):
+        _check(load().kk_sync(self._h))
+
+    def sweep_timed(self, n: int) -> Tuple[float, int]:
+        ms = ctypes.c_double()
+        nl = ctypes.c_uint64()
+        _check(load().kk_sweep_timed(self._h, n, ctypes.byref(ms), ctypes.byref(nl)))
+        return ms.value, nl.value
+
+    def energy(self) -> Tuple[int, float]:
+        n = ctypes.c_uint64()
+        e = ctypes.c_double()
+        _check(load().kk_energy(self._h, ctypes.byref(n), ctypes.byref(e)))
+        return n.value, e.value
+
+    def cluster_hist(self, species: int = 1) -> List[Tuple[int, int]]:
+        lib = load()
+        need = ctypes.c_size_t()
+        st = lib.kk_cluster_hist(self._h, species, None, 0, ctypes.byref(need))
+        if st not in (KK_OK, KK_ETRUNC):
+            _check(st)
+        buf = (HistEntry * max(1, need.value))()
+        _check(lib.kk_cluster_hist(self._h, species, buf, need.value, ctypes.byref(need)))
+        return [(int(buf[i].size), int(buf[i].count)) for i in range(need.value)]
+
+    def get_lattice(self) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.uint8)
+        _check(load().kk_get_lattice(self._h, out.ctypes.data, out.size))
+        return out
+
+    def set_lattice(self, s: np.ndarray, sweep_t: int = 0):
+        s = np.ascontiguousarray(s, dtype=np.uint8)
+        if s.shape != (self.L, self.L):
+            raise ValueError(f"lattice must be {self.L}x{self.L}")
+        _check(load().kk_set_lattice(self._h, s.ctypes.data, s.size, sweep_t))
+
+    def stats(self) -> Tuple[int, int, int]:
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().kk_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def thresholds(self) -> np.ndarray:
+        out = np.zeros(7, dtype=np.uint64)
+        _check(load().kk_thresholds(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out
+
+    def info(self) -> Tuple[int, str]:
+        L, lay = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().kk_info(self._h, ctypes.byref(L), ctypes.byref(lay)))
+        return L.value, {LAYOUT_INT8: "int8", LAYOUT_BITPACKED: "bitpacked"}[lay.value]
+
+    def set_tile(self, words: int, rows: int, units_per_thread: int = 2):
+        _check(load().kk_set_tile(self._h, words, rows, units_per_thread))
+
+    def get_tile(self) -> Tuple[int, int, int]:
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().kk_get_tile(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def stream(self) -> int:
+        p = ctypes.c_void_p()
+        _check(load().kk_stream(self._h, ctypes.byref(p)))
+        return p.value or 0
