@@ -1,0 +1,177 @@
+"""Benchmark: Kawasaki swap attempts per second on a 4096x4096 bit-packed lattice.
+
+One step is one pass of the hot path over the standing 4096^2 workload
+(composition 0.5, omega = 0.88 kT, bit-packed, lattice resident in HBM):
+10,000 sweeps (N = 16.8 M attempts each), then N_AB and the cluster-size
+histogram of species 1.  The line also carries:
+  * roofline -- the sweep kernel's algorithmic integer-op rate against the
+    VALU peak, and its algorithmic bytes against HBM peak (measured with HIP
+    events around every sweep launch on the library's stream);
+  * cpu_baseline -- the CPU oracle timed on a bounded sample of the same
+    workload on this host;
+  * batched -- aggregate attempts/s of the batch engine against the same
+    replicas run one after another through the plain path (when available).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts
+HBM_PEAK_GBS = 8000.0
+CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
+VALU_PEAK_GOPS = CUS * LANES * CLOCK_HZ / 1e9   # int32 lane-ops/s, one VALU op per lane per clock
+
+# Algorithmic cost of one attempt of the bit-sliced sweep (derivation in the design notes):
+#   random planes: 3 Philox4x32-10 blocks per 32 sites per sweep, 40 VALU ops per block
+#   (10 rounds x [2 v_mad_u64_u32 + 2 v_xor3]) -> 120/32 = 3.75 ops per attempt;
+#   decision of 8 centres per 32-site word per phase: 116 ops -> 14.5 ops per attempt.
+OPS_PER_ATTEMPT = 3.75 + 14.5
+BYTES_PER_ATTEMPT_BITS = 0.25   # read + write one bit per site per sweep
+BYTES_PER_ATTEMPT_INT8 = 2.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(job, budget_s: float = 12.0):
+    """Time the CPU oracle (as it stands) on whole sweeps of the same lattice."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.init(job.L, job.composition, job.seed)
+    t0 = time.perf_counter()
+    oracle.sweeps(s, job.omega, job.seed, 0, 1)
+    one = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    oracle.sweeps(s, job.omega, job.seed, 1, n)
+    dt = time.perf_counter() - t0
+    rate = n * job.L * job.L / dt
+    return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} sweeps of the {job.L}x{job.L} x={job.composition} omega={job.omega} lattice "
+                      f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=10_000, help="sweeps per step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(replicas shard trivially across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1309_4349_amd import kk
+    from paper_1309_4349_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4}))
+        return
+
+    job = wl.big_4096(args.sweeps)
+    N = job.L * job.L
+    log(f"[bench] creating {job.tag}")
+    sim = kk.Sim(job.L, job.composition, job.omega, job.seed, layout="bitpacked")
+
+    def step():
+        sim.sweep(job.sweeps)
+        sim.energy()
+        sim.cluster_hist(1)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"[bench] step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    attempts = args.steps * job.sweeps * N
+    value = attempts / dt
+    nab, _ = sim.energy()
+    log(f"[bench] {value:.4e} attempts/s, N_AB/2N = {nab / (2 * N):.5f}")
+
+    # roofline of the sweep kernel: HIP events around every launch on the library's stream
+    ms, launches = sim.sweep_timed(args.profile_sweeps)
+    per_launch_s = ms / 1e3 / launches
+    attempts_per_launch = N * args.profile_sweeps / launches
+    ops = OPS_PER_ATTEMPT * attempts_per_launch / per_launch_s / 1e9
+    hbm = BYTES_PER_ATTEMPT_BITS * attempts_per_launch / per_launch_s / 1e9
+    tw, th, ku = sim.get_tile()
+    roofline = {"bound": "alu", "achieved": round(ops, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
+                "frac": round(ops / VALU_PEAK_GOPS, 4), "traffic": None,
+                "kernel": "sweep_kernel<bitpacked, halo tiles>",
+                "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
+                "ops_per_attempt": OPS_PER_ATTEMPT,
+                "hbm_achieved_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
+                "hbm_frac": round(hbm / HBM_PEAK_GBS, 5),
+                "tile": {"words": tw, "rows": th, "units_per_thread": ku}}
+    log(f"[bench] sweep kernel {per_launch_s * 1e6:.2f} us/launch, {ops:.0f} Gop/s, {hbm:.1f} GB/s algorithmic")
+    sim.close()
+
+    batched = None
+    if not args.no_batch:
+        try:
+            from paper_1309_4349_amd import batch as kb
+            batched = kb.bench_batched_vs_plain(log=log)
+        except ImportError:
+            batched = None
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle")
+        cpu = cpu_baseline(job)
+        log(f"[bench] oracle {cpu['value']:.3e} attempts/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": "Kawasaki swap attempts/sec (4096^2 bit-packed lattice, omega=0.88, x=0.5)",
+        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u1 (1 bit/site), int32 SWAR", "data": "synthetic",
+        "config": {"workload": job.tag + f", {job.sweeps} sweeps + N_AB + cluster histogram per step",
+                   "L": job.L, "composition": job.composition, "omega": job.omega,
+                   "sweeps_per_step": job.sweeps, "layout": "bitpacked"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if batched is not None:
+        line["batched"] = batched
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
