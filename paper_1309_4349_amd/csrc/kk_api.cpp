@@ -138,7 +138,10 @@ struct kk_sim {
   uint64_t attempts = 0;
   void* lat[2] = {nullptr, nullptr};
   int cur = 0;
-  unsigned long long* counters = nullptr;  // [0] accepted, [1] energy scratch
+  unsigned long long* counters = nullptr;  // [0] unused, [1] energy scratch
+  unsigned long long* partials = nullptr;  // accepted moves, one running sum per sweep tile
+  size_t npartials = 0;
+  uint64_t accepted_base = 0;              // accepted moves folded in from earlier tile shapes
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
@@ -176,6 +179,7 @@ void free_all(kk_sim* h) {
   for (int i = 0; i < 2; ++i)
     if (h->lat[i]) (void)hipFree(h->lat[i]);
   if (h->counters) (void)hipFree(h->counters);
+  if (h->partials) (void)hipFree(h->partials);
   if (h->ccl.parent) (void)hipFree(h->ccl.parent);
   if (h->ccl.size) (void)hipFree(h->ccl.size);
   if (h->ccl.hist) (void)hipFree(h->ccl.hist);
@@ -284,12 +288,53 @@ kk_status place_initial(kk_sim* h) {
   return KK_OK;
 }
 
+size_t tile_count(int L, const TileConfig& tc) {
+  SweepParams p{};
+  tile_geometry(L, tc, &p);
+  return (size_t)p.tiles_x * (size_t)((L + p.th - 1) / p.th);
+}
+
+uint64_t sum_partials(kk_sim* h, kk_status* st) {
+  std::vector<unsigned long long> v(h->npartials);
+  *st = KK_OK;
+  hipError_t e = hipMemcpyAsync(v.data(), h->partials, h->npartials * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    *st = set_error(KK_EDEVICE, "reading accepted counts: %s", hipGetErrorString(e));
+    return 0;
+  }
+  uint64_t s = 0;
+  for (auto x : v) s += x;
+  return s;
+}
+
+// Size the per-tile accepted-move sums for the current tile shape, folding
+// the counts gathered under the previous shape into accepted_base.
+kk_status reset_partials(kk_sim* h) {
+  if (h->partials) {
+    kk_status st;
+    const uint64_t s = sum_partials(h, &st);
+    if (st != KK_OK) return st;
+    h->accepted_base += s;
+    (void)hipFree(h->partials);
+    h->partials = nullptr;
+  }
+  h->npartials = tile_count(h->L, h->tile);
+  kk_status st = dmalloc(h, (void**)&h->partials, h->npartials * sizeof(unsigned long long));
+  if (st != KK_OK) return st;
+  KK_HIP(hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  return KK_OK;
+}
+
 // Launch sweeps [h->t, h->t + n) on the handle's stream.  With `timing`, an
 // event pair brackets every launch and the kernel time is accumulated.
 kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
   SweepParams p{};
   const int threads = tile_geometry(h->L, h->tile, &p);
-  p.accepted = h->counters;
+  p.accepted = h->partials;
   p.k0 = h->k0;
   p.k1 = h->k1;
   p.acc = h->acc;
@@ -400,6 +445,7 @@ kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omeg
     e = hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned long long), h->stream);
     if (e != hipSuccess) st = set_error(KK_EDEVICE, "memset failed: %s", hipGetErrorString(e));
   }
+  if (st == KK_OK) st = reset_partials(h);
   if (st == KK_OK) st = place_initial(h);
   if (st != KK_OK) {
     free_all(h);
@@ -550,9 +596,9 @@ kk_status kk_set_lattice(kk_sim* h, const uint8_t* host_in, size_t n, uint64_t s
 
 kk_status kk_stats(kk_sim* h, uint64_t* sweeps, uint64_t* attempts, uint64_t* accepted) {
   KK_GUARD(h);
-  unsigned long long acc = 0;
-  KK_HIP(hipMemcpyAsync(&acc, h->counters, sizeof acc, hipMemcpyDeviceToHost, h->stream));
-  KK_HIP(hipStreamSynchronize(h->stream));
+  kk_status st;
+  const uint64_t acc = h->accepted_base + sum_partials(h, &st);
+  if (st != KK_OK) return st;
   if (sweeps) *sweeps = h->t;
   if (attempts) *attempts = h->attempts;
   if (accepted) *accepted = acc;
@@ -589,7 +635,7 @@ kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32
   std::string why;
   if (!tile_valid(h->L, tc, &why)) return set_error(KK_EINVAL, "invalid tile: %s", why.c_str());
   h->tile = tc;
-  return KK_OK;
+  return reset_partials(h);
 }
 
 kk_status kk_get_tile(kk_sim* h, uint32_t* tile_words, uint32_t* tile_rows, uint32_t* units_per_thread) {

@@ -14,7 +14,7 @@ constexpr int kLayoutBits = 2;  // one bit per site, L/32 words per row, bit b o
 struct SweepParams {
   const void* src;
   void* dst;
-  unsigned long long* accepted;
+  unsigned long long* accepted;  // one running sum per tile (grid index)
   int L, wpr;                // side; words per row of the bit-packed layout
   int tww, th;               // interior words / rows per tile
   int hx, hy;                // halo words / rows on each side (1/16, or 0/0 for the cyclic tile)

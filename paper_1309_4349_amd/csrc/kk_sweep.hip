@@ -345,10 +345,20 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void sweep_kernel(SweepParams
     store_word<LAYOUT>(p, Y0 + rr, x0, nb == 32 ? v : (v & ((1u << nb) - 1u)), nb);
   }
 
-  // accepted-move count: wave reduction, one atomic per wave
-  unsigned long long c = count;
+  // Accepted-move count: reduce over the workgroup, then one plain
+  // read-modify-write of this tile's own partial sum.  (One device-scope
+  // atomic per wave on a single address serialises across the XCDs and
+  // cost more than the sweep itself.)
+  unsigned c = count;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(p.accepted, c);
+  unsigned* red = reinterpret_cast<unsigned*>(S + p.R * stride);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
+    p.accepted[tile] += tot;
+  }
 }
 
 }  // namespace
@@ -356,7 +366,7 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void sweep_kernel(SweepParams
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream) {
   const int tiles_y = (p.L + p.th - 1) / p.th;
   const dim3 grid(p.tiles_x * tiles_y), block(threads);
-  const size_t lds = (size_t)p.R * (p.C + 2) * sizeof(uint32_t);
+  const size_t lds = (size_t)p.R * (p.C + 2) * sizeof(uint32_t) + 16 * sizeof(unsigned);
 #define KK_LAUNCH(LY, CY, KUV) hipLaunchKernelGGL((sweep_kernel<LY, CY, KUV>), grid, block, lds, stream, p)
   if (layout == kLayoutBits) {
     if (cyclic) { if (ku == 1) KK_LAUNCH(kLayoutBits, true, 1); else KK_LAUNCH(kLayoutBits, true, 2); }
