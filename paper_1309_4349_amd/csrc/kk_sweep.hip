@@ -142,6 +142,53 @@ __device__ void gen_planes(const SweepParams& p, int yv, int Xw, uint64_t t, uin
   }
 }
 
+
+// Bit-packed or int8 word at true row y, 32 sites from true x0 (which may
+// straddle the periodic wrap only when L % 32 != 0 or L < 32).
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t load_word_at(const SweepParams& p, int y, int x0) {
+  if (LAYOUT == kLayoutBits) return static_cast<const uint32_t*>(p.src)[(size_t)y * p.wpr + (x0 >> 5)];
+  const int L = p.L;
+  const uint8_t* row = static_cast<const uint8_t*>(p.src) + (size_t)y * L;
+  if (x0 + 32 <= L) {
+    uint32_t v = 0;
+    if ((L & 15) == 0) {
+      const uint4* d = reinterpret_cast<const uint4*>(row + x0);
+      const uint4 a = d[0], b = d[1];
+      v = pack4(a.x) | (pack4(a.y) << 4) | (pack4(a.z) << 8) | (pack4(a.w) << 12) | (pack4(b.x) << 16) |
+          (pack4(b.y) << 20) | (pack4(b.z) << 24) | (pack4(b.w) << 28);
+    } else {
+      const uint32_t* d = reinterpret_cast<const uint32_t*>(row + x0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v |= pack4(d[k]) << (4 * k);
+    }
+    return v;
+  }
+  uint32_t v = 0;
+  int x = x0;
+  for (int b = 0; b < 32; ++b) {
+    v |= (uint32_t)(row[x] & 1u) << b;
+    x = (x + 1 == L) ? 0 : x + 1;
+  }
+  return v;
+}
+
+// Random planes of the 32 sites starting at true column x0 of true row y.
+__device__ __forceinline__ void gen_planes_at(const SweepParams& p, int y, int x0, int Xw, uint64_t t, uint32_t* pl) {
+  if ((x0 & 31) == 0 && x0 + 32 <= p.L) {
+    const uint32_t tl = (uint32_t)t, thi = ctr_hi(t, kTagSweep);
+    const uint32_t g4 = (uint32_t)(x0 >> 5) * 4u;
+    const Philox4 a = philox10((uint32_t)y, g4 + 0u, tl, thi, p.k0, p.k1);
+    const Philox4 b = philox10((uint32_t)y, g4 + 1u, tl, thi, p.k0, p.k1);
+    const Philox4 c = philox10((uint32_t)y, g4 + 2u, tl, thi, p.k0, p.k1);
+    pl[0] = a.x; pl[1] = a.y; pl[2] = a.z; pl[3] = a.w;
+    pl[4] = b.x; pl[5] = b.y; pl[6] = b.z; pl[7] = b.w;
+    pl[8] = c.x; pl[9] = c.y; pl[10] = c.z; pl[11] = c.w;
+    return;
+  }
+  gen_planes(p, y, Xw, t, pl);
+}
+
 // 10-bit (u < K) and (u == K) over bit-sliced u, planes[2] = MSB .. planes[11] = LSB,
 // processed from the least significant bit: lt' = maj(~u_k, K_k, lt).
 __device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& lt, uint32_t& eq) {
@@ -361,12 +408,275 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void sweep_kernel(SweepParams
   }
 }
 
+
+// Per-row random state for one sweep: the two direction planes and, for each
+// of the three rejectable classes of moves, (u10 < T_hi) and (u10 == T_hi)
+// over the row's 32 sites.  8 words replace the 12 random planes once the
+// comparisons are done.
+struct RowRand {
+  uint32_t d0, d1, lt0, lt1, lt2, eq0, eq1, eq2;
+};
+
+__device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& p, RowRand& q) {
+  q.d0 = pl[0];
+  q.d1 = pl[1];
+  if (p.acc.hi[0] < 1024u) cmp10(pl, p.acc.hi[0], q.lt0, q.eq0); else { q.lt0 = 0xFFFFFFFFu; q.eq0 = 0u; }
+  if (p.acc.hi[1] < 1024u) cmp10(pl, p.acc.hi[1], q.lt1, q.eq1); else { q.lt1 = 0xFFFFFFFFu; q.eq1 = 0u; }
+  if (p.acc.hi[2] < 1024u) cmp10(pl, p.acc.hi[2], q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
+}
+
+// Decide the exchanges of the centres in `cmask` of one 32-site word.
+// v: the word (0), its west/east neighbours (1, 2), the same three in the
+// row above (3..5) and below (6..8), and the words two rows above / below
+// (9, 10).  Returns the accepted centres.
+__device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand& q, const SweepParams& p,
+                                                uint32_t cmask, int yv, int Xw, uint64_t t) {
+  const uint32_t c0 = v[0], n0 = v[3], s0 = v[6];
+  const uint32_t cE = __builtin_amdgcn_alignbit(v[2], c0, 1);
+  const uint32_t cW = __builtin_amdgcn_alignbit(c0, v[1], 31);
+  const uint32_t cE2 = __builtin_amdgcn_alignbit(v[2], c0, 2);
+  const uint32_t cW2 = __builtin_amdgcn_alignbit(c0, v[1], 30);
+  const uint32_t nE = __builtin_amdgcn_alignbit(v[5], n0, 1);
+  const uint32_t nW = __builtin_amdgcn_alignbit(n0, v[4], 31);
+  const uint32_t sE = __builtin_amdgcn_alignbit(v[8], s0, 1);
+  const uint32_t sW = __builtin_amdgcn_alignbit(s0, v[7], 31);
+  const uint32_t d0 = q.d0, d1 = q.d1;
+  const uint32_t B = sel4(d1, d0, cE, cW, s0, n0);
+  const uint32_t A = (c0 ^ B) & cmask;
+  const uint32_t o1 = sel4(d1, d0, cE2, cW2, v[10], v[9]);
+  const uint32_t o2 = sel4(d1, d0, nE, nW, sW, nW);
+  const uint32_t o3 = sel4(d1, d0, sE, sW, sE, nE);
+  const uint32_t uE = c0 ^ cE, uW = c0 ^ cW, uN = c0 ^ n0, uS = c0 ^ s0;
+  const uint32_t e1 = ~(c0 ^ o1), e2 = ~(c0 ^ o2), e3 = ~(c0 ^ o3);
+  const uint32_t s1 = uE ^ uW ^ uN, c1 = maj3(uE, uW, uN);
+  const uint32_t s2 = uS ^ e1 ^ e2, c2 = maj3(uS, e1, e2);
+  const uint32_t m0 = s1 ^ s2 ^ e3, c3 = maj3(s1, s2, e3);
+  const uint32_t m1 = c1 ^ c2 ^ c3, m2 = maj3(c1, c2, c3);
+  uint32_t F = A;
+  if (p.acc.restricted) {
+    const uint32_t rm = ~(m2 ^ p.acc.negmask) & (m0 | m1);
+    const uint32_t ltsel = (m1 & ((m0 & q.lt2) | (~m0 & q.lt1))) | (~m1 & q.lt0);
+    const uint32_t eqsel = (m1 & ((m0 & q.eq2) | (~m0 & q.eq1))) | (~m1 & q.eq0);
+    F = A & (~rm | ltsel);
+    uint32_t tie = A & rm & eqsel;
+    while (tie) {  // u10 equals the threshold prefix: draw the low 32 bits
+      const int bp = __builtin_ctz(tie);
+      tie &= tie - 1u;
+      const uint32_t x = (uint32_t)imod(Xw + bp, p.L), y = (uint32_t)imod(yv, p.L);
+      const Philox4 e = philox10(y, x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
+      const uint32_t xs = x & 3u;
+      const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
+      const uint32_t j = ((((m1 >> bp) & 1u) << 1) | ((m0 >> bp) & 1u)) - 1u;
+      const uint32_t lo = j == 0 ? p.acc.lo[0] : j == 1 ? p.acc.lo[1] : p.acc.lo[2];
+      if (ext < lo) F |= 1u << bp;
+    }
+  }
+  return F;
+}
+
+template <int TWW>
+struct HaloGeom {
+  static constexpr int C = TWW + 2;  // LDS words per row: the tile plus one halo word each side
+  // Row stride: at least C + 2 (one pad word each side), and congruent to
+  // C/2 modulo 32 so that the words a phase touches (every other row,
+  // consecutive words) fall in consecutive LDS banks.
+  static constexpr int ST = (C % 2 == 0) ? (C / 2 + 32) : 34;
+};
+
+// One phase of the halo kernel for the thread's units, active row = r0 + H.
+// Branch-free over the units: a unit beyond the tile reads a valid word and
+// has an empty centre mask, so it decides nothing and writes nothing.
+template <int TWW, int KU, int H>
+__device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p, const int* base0, const int* yrow,
+                                               const int* xw, const uint32_t* okm, const RowRand (*rr)[2],
+                                               const uint32_t (*imask)[2], int a, uint64_t t) {
+  constexpr int ST = HaloGeom<TWW>::ST;
+  uint32_t v[KU][11];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int b = base0[k] + H * ST;
+    v[k][0] = S[b];
+    v[k][1] = S[b - 1];
+    v[k][2] = S[b + 1];
+    v[k][3] = S[b - ST];
+    v[k][4] = S[b - ST - 1];
+    v[k][5] = S[b - ST + 1];
+    v[k][6] = S[b + ST];
+    v[k][7] = S[b + ST - 1];
+    v[k][8] = S[b + ST + 1];
+    v[k][9] = S[b - 2 * ST];
+    v[k][10] = S[b + 2 * ST];
+  }
+  uint32_t F[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int yv = yrow[k] + H;
+    F[k] = decide_word(v[k], rr[k][H], p, (0x11111111u << ((a + yv) & 3)) & okm[k], yv, xw[k], t);
+  }
+  unsigned count = 0;
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const uint32_t d0 = rr[k][H].d0, d1 = rr[k][H].d1;
+    const uint32_t f = F[k];
+    const uint32_t Fpx = f & ~d1 & ~d0, Fmx = f & ~d1 & d0;
+    const uint32_t Fpy = f & d1 & ~d0, Fmy = f & d1 & d0;
+    const int b = base0[k] + H * ST;
+    // zero masks are harmless: the three common updates go out unconditionally
+    atomicXor(&S[b], f ^ (Fpx << 1) ^ (Fmx >> 1));
+    atomicXor(&S[b + ST], Fpy);
+    atomicXor(&S[b - ST], Fmy);
+    if (Fpx >> 31) atomicXor(&S[b + 1], 1u);
+    if (Fmx & 1u) atomicXor(&S[b - 1], 0x80000000u);
+    count += (unsigned)__builtin_popcount(f & imask[k][H]);
+  }
+  return count;
+}
+
+// Halo-tile sweep with a compile-time tile width: the LDS row stride is a
+// constant, so every neighbour of a unit is an immediate offset from one
+// base address.  Each thread owns KU (row pair, word) units; their random
+// state lives in registers for the whole sweep.  In a phase the thread reads
+// the neighbourhoods of all its units before issuing any exchange (the
+// conflict-free schedule makes that reordering exact), so the LDS latency of
+// the second unit hides behind the first.
+template <int LAYOUT, int TWW, int KU>
+__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams p) {
+  constexpr int C = HaloGeom<TWW>::C;
+  constexpr int ST = HaloGeom<TWW>::ST;
+  constexpr int CP = C + 2;   // staged words per row (the pads included)
+  constexpr int NSTG = 6;     // staged global words per thread
+  extern __shared__ uint32_t S[];
+  const int tile = blockIdx.x;
+  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+  const int X0 = tx * TWW * 32, Y0 = ty * p.th;
+  const int XL = X0 - 32, YT = Y0 - 16;
+  const int xend = min(X0 + TWW * 32, p.L), yend = min(Y0 + p.th, p.L);
+  const int total = p.R * CP;
+  const uint64_t t = p.t0;
+  // true (wrapped) row of every LDS row and true column of every LDS word
+  int* ytab = reinterpret_cast<int*>(S + p.R * ST + 16);
+  int* xtab = ytab + p.R;
+  for (int i = threadIdx.x; i < p.R + C; i += blockDim.x) {
+    if (i < p.R) ytab[i] = imod(YT + i, p.L);
+    else xtab[i - p.R] = imod(XL + 32 * (i - p.R), p.L);
+  }
+  __syncthreads();
+
+  // global loads first; they complete while the random state is computed
+  uint32_t stg[NSTG];
+#pragma unroll
+  for (int j = 0; j < NSTG; ++j) {
+    const int i = threadIdx.x + j * blockDim.x;
+    const int r = i / CP, w = i - r * CP - 1;
+    stg[j] = (i < total && w >= 0 && w < C) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
+  }
+  for (int i = threadIdx.x + NSTG * blockDim.x; i < total; i += blockDim.x) {
+    const int r = i / CP, w = i - r * CP - 1;
+    S[r * ST + w + 1] = (w >= 0 && w < C) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
+  }
+
+  int base0[KU], yrow[KU], xw[KU];
+  uint32_t okm[KU];
+  uint32_t imask[KU][2];
+  RowRand rr[KU][2];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int u = threadIdx.x + k * blockDim.x;
+    const bool ok = u < p.nunits;
+    const int q = ok ? u / C : 0, w = ok ? u - q * C : 0;
+    const int r0 = 2 + 2 * q;
+    base0[k] = r0 * ST + w + 1;
+    yrow[k] = YT + r0;
+    xw[k] = XL + 32 * w;
+    okm[k] = ok ? 0xFFFFFFFFu : 0u;
+    const int Xw = xw[k];
+    uint32_t wm = 0u;
+    if (Xw + 32 > X0 && Xw < xend) {
+      const int lo = max(Xw, X0), hi = min(Xw + 32, xend);
+      const int n = hi - lo;
+      wm = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << (lo - Xw);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int yv = yrow[k] + h;
+      imask[k][h] = (ok && yv >= Y0 && yv < yend) ? wm : 0u;
+      uint32_t pl[kPlanes];
+      gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
+      row_rand(pl, p, rr[k][h]);
+    }
+  }
+  const uint32_t perm = class_order(p.k0, p.k1, t);
+#pragma unroll
+  for (int j = 0; j < NSTG; ++j) {
+    const int i = threadIdx.x + j * blockDim.x;
+    const int r = i / CP, w = i - r * CP;
+    if (i < total) S[r * ST + w] = stg[j];
+  }
+  __syncthreads();
+
+  unsigned count = 0;
+#pragma unroll 1
+  for (int ph = 0; ph < 8; ++ph) {
+    const uint32_t cls = (perm >> (4 * ph)) & 0xFu;
+    const int a = (int)(cls >> 1);
+    // pairs start on even rows, so the active row of every pair is the class
+    // parity: a uniform branch keeps each row's random state in registers
+    if (cls & 1u) count += halo_phase<TWW, KU, 1>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
+    else count += halo_phase<TWW, KU, 0>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
+    __syncthreads();
+  }
+
+  // write the interior back
+  const int iw = (xend - X0 + 31) / 32, ih = yend - Y0;
+  for (int i = threadIdx.x; i < iw * ih; i += blockDim.x) {
+    const int rr2 = i / iw, ww = i - rr2 * iw;
+    const int x0 = X0 + 32 * ww;
+    const int nb = min(32, xend - x0);
+    const uint32_t val = S[(16 + rr2) * ST + 1 + ww + 1];
+    store_word<LAYOUT>(p, Y0 + rr2, x0, nb == 32 ? val : (val & ((1u << nb) - 1u)), nb);
+  }
+
+  unsigned c = count;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  unsigned* red = reinterpret_cast<unsigned*>(S + p.R * ST);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
+    p.accepted[tile] += tot;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream) {
   const int tiles_y = (p.L + p.th - 1) / p.th;
   const dim3 grid(p.tiles_x * tiles_y), block(threads);
   const size_t lds = (size_t)p.R * (p.C + 2) * sizeof(uint32_t) + 16 * sizeof(unsigned);
+  if (!cyclic && (p.tww == 1 || p.tww == 2 || p.tww == 4 || p.tww == 8 || p.tww == 16)) {
+#define KK_HALO(LY, TW)                                                                                  \
+  do {                                                                                                   \
+    const size_t hl = ((size_t)p.R * HaloGeom<TW>::ST + 16 + p.R + HaloGeom<TW>::C) * sizeof(uint32_t);  \
+    if (ku == 1) hipLaunchKernelGGL((halo_kernel<LY, TW, 1>), grid, block, hl, stream, p);               \
+    else hipLaunchKernelGGL((halo_kernel<LY, TW, 2>), grid, block, hl, stream, p);                       \
+  } while (0)
+#define KK_HALO_W(LY)                          \
+  do {                                         \
+    switch (p.tww) {                           \
+      case 1: KK_HALO(LY, 1); break;           \
+      case 2: KK_HALO(LY, 2); break;           \
+      case 4: KK_HALO(LY, 4); break;           \
+      case 8: KK_HALO(LY, 8); break;           \
+      default: KK_HALO(LY, 16); break;         \
+    }                                          \
+  } while (0)
+    if (layout == kLayoutBits) KK_HALO_W(kLayoutBits);
+    else KK_HALO_W(kLayoutInt8);
+#undef KK_HALO_W
+#undef KK_HALO
+    return hipGetLastError();
+  }
 #define KK_LAUNCH(LY, CY, KUV) hipLaunchKernelGGL((sweep_kernel<LY, CY, KUV>), grid, block, lds, stream, p)
   if (layout == kLayoutBits) {
     if (cyclic) { if (ku == 1) KK_LAUNCH(kLayoutBits, true, 1); else KK_LAUNCH(kLayoutBits, true, 2); }
