@@ -62,13 +62,16 @@ void default_tile(int L, int layout, TileConfig* tc) {
     tc->ku = units > max_threads(1) ? 2 : 1;
     return;
   }
-  static const int cand[][2] = {{8, 256}, {8, 128}, {4, 128}, {4, 64}, {2, 64}, {2, 32}};
+  // Largest tile (least halo work) that still gives the GPU enough workgroups;
+  // two units per thread only when the tiles saturate the device.
+  static const int cand[][2] = {{16, 128}, {8, 128}, {8, 64}, {4, 64}, {2, 64}, {2, 32}, {2, 16}, {1, 16}};
   const int ncand = (int)(sizeof cand / sizeof cand[0]);
   int pick = ncand - 1;
+  long tiles = 0;
   for (int i = 0; i < ncand; ++i) {
     const int tww = std::min(cand[i][0], (L + 31) / 32);
     const int th = std::min(cand[i][1], L);
-    const long tiles = (long)((L + 32 * tww - 1) / (32 * tww)) * ((L + th - 1) / th);
+    tiles = (long)((L + 32 * tww - 1) / (32 * tww)) * ((L + th - 1) / th);
     if (tiles >= 128) {
       pick = i;
       break;
@@ -77,7 +80,9 @@ void default_tile(int L, int layout, TileConfig* tc) {
   tc->cyclic = false;
   tc->tww = std::min(cand[pick][0], (L + 31) / 32);
   tc->th = std::min(cand[pick][1], L);
-  tc->ku = 2;
+  // Two units per thread pay off only when the tiles oversubscribe the device;
+  // small lattices are latency-bound and run faster with one.
+  tc->ku = (tiles >= 256 && L >= 2048) ? 2 : 1;
 }
 
 // Fill the geometry fields of p for lattice side L and tile config tc.

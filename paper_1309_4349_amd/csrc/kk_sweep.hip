@@ -425,12 +425,30 @@ __device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& 
   if (p.acc.hi[2] < 1024u) cmp10(pl, p.acc.hi[2], q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
 }
 
+// Three-input bitwise function with a truth table built from the operand
+// patterns a = 0xF0, b = 0xCC, c = 0xAA (one v_bitop3_b32).
+#define KK_TA 0xF0u
+#define KK_TB 0xCCu
+#define KK_TC 0xAAu
+#define KK_TT(expr) ((unsigned)((expr) & 0xFFu))
+template <unsigned TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+// a ? b : c, per bit
+__device__ __forceinline__ uint32_t bsel(uint32_t a, uint32_t b, uint32_t c) {
+  return bop3<KK_TT((KK_TA & KK_TB) | (~KK_TA & KK_TC))>(a, b, c);
+}
+constexpr unsigned kXor3 = KK_TT(KK_TA ^ KK_TB ^ KK_TC);
+constexpr unsigned kMaj3 = KK_TT((KK_TA & KK_TB) | (KK_TA & KK_TC) | (KK_TB & KK_TC));
+
 // Decide the exchanges of the centres in `cmask` of one 32-site word.
 // v: the word (0), its west/east neighbours (1, 2), the same three in the
 // row above (3..5) and below (6..8), and the words two rows above / below
-// (9, 10).  Returns the accepted centres.
+// (9, 10).  (ytrue, xtrue) are the true coordinates of bit 0 (xtrue + b may
+// pass the wrap only for L % 32 != 0 or L < 32).  Returns the accepted centres.
 __device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand& q, const SweepParams& p,
-                                                uint32_t cmask, int yv, int Xw, uint64_t t) {
+                                                uint32_t cmask, int ytrue, int xtrue, uint64_t t) {
   const uint32_t c0 = v[0], n0 = v[3], s0 = v[6];
   const uint32_t cE = __builtin_amdgcn_alignbit(v[2], c0, 1);
   const uint32_t cW = __builtin_amdgcn_alignbit(c0, v[1], 31);
@@ -441,30 +459,38 @@ __device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand
   const uint32_t sE = __builtin_amdgcn_alignbit(v[8], s0, 1);
   const uint32_t sW = __builtin_amdgcn_alignbit(s0, v[7], 31);
   const uint32_t d0 = q.d0, d1 = q.d1;
-  const uint32_t B = sel4(d1, d0, cE, cW, s0, n0);
-  const uint32_t A = (c0 ^ B) & cmask;
-  const uint32_t o1 = sel4(d1, d0, cE2, cW2, v[10], v[9]);
-  const uint32_t o2 = sel4(d1, d0, nE, nW, sW, nW);
-  const uint32_t o3 = sel4(d1, d0, sE, sW, sE, nE);
-  const uint32_t uE = c0 ^ cE, uW = c0 ^ cW, uN = c0 ^ n0, uS = c0 ^ s0;
-  const uint32_t e1 = ~(c0 ^ o1), e2 = ~(c0 ^ o2), e3 = ~(c0 ^ o3);
-  const uint32_t s1 = uE ^ uW ^ uN, c1 = maj3(uE, uW, uN);
-  const uint32_t s2 = uS ^ e1 ^ e2, c2 = maj3(uS, e1, e2);
-  const uint32_t m0 = s1 ^ s2 ^ e3, c3 = maj3(s1, s2, e3);
-  const uint32_t m1 = c1 ^ c2 ^ c3, m2 = maj3(c1, c2, c3);
+  // direction (d1 d0): 0 +x east, 1 -x west, 2 +y the row below, 3 -y the row above.
+  // B: the partner; o1..o3: the partner's neighbours other than the centre.
+  const uint32_t B = bsel(d1, bsel(d0, n0, s0), bsel(d0, cW, cE));
+  const uint32_t o1 = bsel(d1, bsel(d0, v[9], v[10]), bsel(d0, cW2, cE2));
+  const uint32_t o2 = bsel(bop3<KK_TT(KK_TA & ~KK_TB)>(d1, d0, d0), sW, bsel(d0, nW, nE));
+  const uint32_t o3 = bsel(d0, bsel(d1, nE, sW), sE);
+  const uint32_t A = bop3<KK_TT(KK_TA & (KK_TB ^ KK_TC))>(cmask, c0, B);  // active: unlike partner
+  // m = n + 1 = #(neighbours of c unlike c, partner included) + #(o_i equal to c),
+  // summed by a bit-sliced 7 -> 3 counter written relative to c so the xors with c cancel
+  const uint32_t X1 = bop3<kXor3>(cE, cW, n0);
+  const uint32_t M1 = bop3<kMaj3>(cE, cW, n0);
+  const uint32_t X2 = bop3<kXor3>(s0, o1, o2);
+  const uint32_t M2 = bop3<KK_TT((KK_TA & ~KK_TB) | (KK_TA & ~KK_TC) | (~KK_TB & ~KK_TC))>(s0, o1, o2);
+  const uint32_t M3 = bop3<KK_TT((KK_TA & KK_TB) | (KK_TA & ~KK_TC) | (KK_TB & ~KK_TC))>(X1, X2, o3);
+  const uint32_t m0 = ~(bop3<kXor3>(X1, X2, o3) ^ c0);
+  const uint32_t m1 = bop3<kXor3>(M1, M2, M3) ^ c0;
+  const uint32_t m2 = bop3<kMaj3>(M1, M2, M3) ^ c0;
   uint32_t F = A;
   if (p.acc.restricted) {
-    const uint32_t rm = ~(m2 ^ p.acc.negmask) & (m0 | m1);
-    const uint32_t ltsel = (m1 & ((m0 & q.lt2) | (~m0 & q.lt1))) | (~m1 & q.lt0);
-    const uint32_t eqsel = (m1 & ((m0 & q.eq2) | (~m0 & q.eq1))) | (~m1 & q.eq0);
-    F = A & (~rm | ltsel);
-    uint32_t tie = A & rm & eqsel;
-    while (tie) {  // u10 equals the threshold prefix: draw the low 32 bits
+    // rejectable: m in {1,2,3} for omega > 0 (dU = 6,4,2), {5,6,7} for omega < 0
+    const uint32_t rm = bop3<KK_TT(~KK_TA & (KK_TB | KK_TC))>(m2 ^ p.acc.negmask, m0, m1);
+    const uint32_t ltsel = bsel(m1, bsel(m0, q.lt2, q.lt1), q.lt0);
+    const uint32_t eqsel = bsel(m1, bsel(m0, q.eq2, q.eq1), q.eq0);
+    F = bop3<KK_TT(KK_TA & (~KK_TB | KK_TC))>(A, rm, ltsel);
+    uint32_t tie = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(A, rm, eqsel);
+    while (tie) {  // u10 equals the threshold prefix: the low 32 bits decide
       const int bp = __builtin_ctz(tie);
       tie &= tie - 1u;
-      const uint32_t x = (uint32_t)imod(Xw + bp, p.L), y = (uint32_t)imod(yv, p.L);
-      const Philox4 e = philox10(y, x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
-      const uint32_t xs = x & 3u;
+      int x = xtrue + bp;
+      if (x >= p.L) x = imod(x, p.L);
+      const Philox4 e = philox10((uint32_t)ytrue, (uint32_t)x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
+      const uint32_t xs = (uint32_t)x & 3u;
       const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
       const uint32_t j = ((((m1 >> bp) & 1u) << 1) | ((m0 >> bp) & 1u)) - 1u;
       const uint32_t lo = j == 0 ? p.acc.lo[0] : j == 1 ? p.acc.lo[1] : p.acc.lo[2];
@@ -510,16 +536,19 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
   uint32_t F[KU];
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
-    const int yv = yrow[k] + H;
-    F[k] = decide_word(v[k], rr[k][H], p, (0x11111111u << ((a + yv) & 3)) & okm[k], yv, xw[k], t);
+    // class mask: the unit's base pattern rotated left by a (its period is 4)
+    const uint32_t cmask = __builtin_amdgcn_alignbit(okm[k * 2 + H], okm[k * 2 + H], (32 - a) & 31);
+    F[k] = decide_word(v[k], rr[k][H], p, cmask, yrow[k * 2 + H], xw[k], t);
   }
   unsigned count = 0;
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
     const uint32_t d0 = rr[k][H].d0, d1 = rr[k][H].d1;
     const uint32_t f = F[k];
-    const uint32_t Fpx = f & ~d1 & ~d0, Fmx = f & ~d1 & d0;
-    const uint32_t Fpy = f & d1 & ~d0, Fmy = f & d1 & d0;
+    const uint32_t Fpx = bop3<KK_TT(KK_TA & ~KK_TB & ~KK_TC)>(f, d1, d0);
+    const uint32_t Fmx = bop3<KK_TT(KK_TA & ~KK_TB & KK_TC)>(f, d1, d0);
+    const uint32_t Fpy = bop3<KK_TT(KK_TA & KK_TB & ~KK_TC)>(f, d1, d0);
+    const uint32_t Fmy = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(f, d1, d0);
     const int b = base0[k] + H * ST;
     // zero masks are harmless: the three common updates go out unconditionally
     atomicXor(&S[b], f ^ (Fpx << 1) ^ (Fmx >> 1));
@@ -575,8 +604,8 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams 
     S[r * ST + w + 1] = (w >= 0 && w < C) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
   }
 
-  int base0[KU], yrow[KU], xw[KU];
-  uint32_t okm[KU];
+  int base0[KU], yrow[KU * 2], xw[KU];  // LDS base; true row of each of the pair's rows; true x of bit 0
+  uint32_t okm[KU * 2];                 // class-0 centre pattern of each row (0 for a unit beyond the tile)
   uint32_t imask[KU][2];
   RowRand rr[KU][2];
 #pragma unroll
@@ -586,10 +615,14 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams 
     const int q = ok ? u / C : 0, w = ok ? u - q * C : 0;
     const int r0 = 2 + 2 * q;
     base0[k] = r0 * ST + w + 1;
-    yrow[k] = YT + r0;
-    xw[k] = XL + 32 * w;
-    okm[k] = ok ? 0xFFFFFFFFu : 0u;
-    const int Xw = xw[k];
+    yrow[2 * k] = ytab[r0];
+    yrow[2 * k + 1] = ytab[r0 + 1];
+    xw[k] = xtab[w];
+    // class a = 0 centres of a row with virtual y sit at x = y (mod 4); the
+    // virtual x of bit 0 is a multiple of 32
+    okm[2 * k] = ok ? (0x11111111u << ((YT + r0) & 3)) : 0u;
+    okm[2 * k + 1] = ok ? (0x11111111u << ((YT + r0 + 1) & 3)) : 0u;
+    const int Xw = XL + 32 * w;
     uint32_t wm = 0u;
     if (Xw + 32 > X0 && Xw < xend) {
       const int lo = max(Xw, X0), hi = min(Xw + 32, xend);
@@ -598,7 +631,7 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams 
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int yv = yrow[k] + h;
+      const int yv = YT + r0 + h;
       imask[k][h] = (ok && yv >= Y0 && yv < yend) ? wm : 0u;
       uint32_t pl[kPlanes];
       gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
@@ -648,12 +681,207 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Cyclic whole-lattice tile (L % 32 == 0, C = L/32 words per row).  The
+// lattice rows -2..L+1 and words -1..C are all present in LDS: the ones
+// outside 0..L-1 / 0..C-1 are mirror copies of the wrapped sites, so every
+// neighbour read is an immediate offset as in the halo kernel.  Every
+// exchange is written to all LDS copies of the sites it flips; a unit near
+// the wrap carries a small descriptor of which of its targets have a copy.
+// ---------------------------------------------------------------------------
+template <int C>
+struct CycGeom {
+  static constexpr int ST = (C % 2 == 0) ? (C / 2 + 32) : 34;  // see HaloGeom
+};
+
+// Row copy delta (in LDS rows) of lattice row x in [-2, R+1]: +R, -R or 0.
+__device__ __forceinline__ int row_copy(int x, int R) { return x <= 1 ? R : (x >= R - 2 ? -R : 0); }
+// Word copy delta of word x in [-1, C] (C >= 2): +C, -C or 0.
+template <int C>
+__device__ __forceinline__ int word_copy(int x) { return x <= 0 ? C : (x >= C - 1 ? -C : 0); }
+
+__device__ __forceinline__ void xor_copies(uint32_t* S, int idx, uint32_t m, int dr, int dw) {
+  if (!m) return;
+  if (dr) atomicXor(&S[idx + dr], m);
+  if (dw) atomicXor(&S[idx + dw], m);
+  if (dr && dw) atomicXor(&S[idx + dr + dw], m);
+}
+
+template <int C, int KU, int H>
+__device__ __forceinline__ unsigned cyc_phase(uint32_t* S, const SweepParams& p, const int* base0, const int* yrow,
+                                              const int* xw, const uint32_t* okm, const RowRand (*rr)[2],
+                                              const int* ur, const int* uw, int a, uint64_t t) {
+  constexpr int ST = CycGeom<C>::ST;
+  uint32_t v[KU][11];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int b = base0[k] + H * ST;
+    v[k][0] = S[b];
+    v[k][1] = S[b - 1];
+    v[k][2] = S[b + 1];
+    v[k][3] = S[b - ST];
+    v[k][4] = S[b - ST - 1];
+    v[k][5] = S[b - ST + 1];
+    v[k][6] = S[b + ST];
+    v[k][7] = S[b + ST - 1];
+    v[k][8] = S[b + ST + 1];
+    v[k][9] = S[b - 2 * ST];
+    v[k][10] = S[b + 2 * ST];
+  }
+  uint32_t F[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const uint32_t cmask = __builtin_amdgcn_alignbit(okm[k * 2 + H], okm[k * 2 + H], (32 - a) & 31);
+    F[k] = decide_word(v[k], rr[k][H], p, cmask, yrow[k * 2 + H], xw[k], t);
+  }
+  unsigned count = 0;
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const uint32_t d0 = rr[k][H].d0, d1 = rr[k][H].d1;
+    const uint32_t f = F[k];
+    const uint32_t Fpx = bop3<KK_TT(KK_TA & ~KK_TB & ~KK_TC)>(f, d1, d0);
+    const uint32_t Fmx = bop3<KK_TT(KK_TA & ~KK_TB & KK_TC)>(f, d1, d0);
+    const uint32_t Fpy = bop3<KK_TT(KK_TA & KK_TB & ~KK_TC)>(f, d1, d0);
+    const uint32_t Fmy = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(f, d1, d0);
+    const int b = base0[k] + H * ST;
+    const uint32_t main = f ^ (Fpx << 1) ^ (Fmx >> 1);
+    const uint32_t cr = Fpx >> 31, cl = (Fmx & 1u) << 31;
+    atomicXor(&S[b], main);
+    atomicXor(&S[b + ST], Fpy);
+    atomicXor(&S[b - ST], Fmy);
+    if (cr) atomicXor(&S[b + 1], cr);
+    if (cl) atomicXor(&S[b - 1], cl);
+    const int r = ur[k] + H, w = uw[k];
+    if (f && (r <= 2 || r >= p.R - 3 || w <= 1 || w >= C - 2)) {  // some target has a mirror copy
+      const int R = p.R;
+      const int dr0 = row_copy(r, R) * ST, drp = row_copy(r + 1, R) * ST, drm = row_copy(r - 1, R) * ST;
+      const int dw0 = word_copy<C>(w), dwp = word_copy<C>(w + 1), dwm = word_copy<C>(w - 1);
+      xor_copies(S, b, main, dr0, dw0);
+      xor_copies(S, b + ST, Fpy, drp, dw0);
+      xor_copies(S, b - ST, Fmy, drm, dw0);
+      xor_copies(S, b + 1, cr, dr0, dwp);
+      xor_copies(S, b - 1, cl, dr0, dwm);
+    }
+    count += (unsigned)__builtin_popcount(f & okm[k * 2 + H + 2 * KU]);
+  }
+  return count;
+}
+
+// Whole lattice in one workgroup, p.nsweeps sweeps from p.t0.  Returns the
+// thread's accepted count.
+template <int LAYOUT, int C, int KU>
+__device__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
+  constexpr int ST = CycGeom<C>::ST;
+  const int R = p.R;  // == L
+  const int L = p.L;
+  // stage rows -2..R+1, words -1..C (the copies included)
+  const int rows = R + 4, cols = C + 2;
+  for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
+    const int rr = i / cols, ww = i - rr * cols;
+    int y = rr - 2, x = ww - 1;
+    y = y < 0 ? y + R : (y >= R ? y - R : y);
+    x = x < 0 ? x + C : (x >= C ? x - C : x);
+    S[rr * ST + ww] = load_word_at<LAYOUT>(p, y, 32 * x);
+  }
+  int base0[KU], yrow[KU * 2], xw[KU], ur[KU], uw[KU];
+  uint32_t okm[KU * 4];  // [0, 2KU): class-0 pattern per row; [2KU, 4KU): count mask per row
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int u = threadIdx.x + k * blockDim.x;
+    const bool ok = u < p.nunits;
+    const int q = ok ? u / C : 0, w = ok ? u - q * C : 0;
+    const int r0 = 2 * q;  // lattice row of the pair's first row
+    base0[k] = (r0 + 2) * ST + w + 1;
+    ur[k] = r0;
+    uw[k] = w;
+    yrow[2 * k] = r0;
+    yrow[2 * k + 1] = r0 + 1;
+    xw[k] = 32 * w;
+    okm[2 * k] = ok ? (0x11111111u << (r0 & 3)) : 0u;
+    okm[2 * k + 1] = ok ? (0x11111111u << ((r0 + 1) & 3)) : 0u;
+    okm[2 * KU + 2 * k] = ok ? 0xFFFFFFFFu : 0u;
+    okm[2 * KU + 2 * k + 1] = ok ? 0xFFFFFFFFu : 0u;
+  }
+  (void)L;
+  unsigned count = 0;
+#pragma unroll 1
+  for (int s = 0; s < p.nsweeps; ++s) {
+    const uint64_t t = p.t0 + (uint64_t)s;
+    RowRand rr[KU][2];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t pl[kPlanes];
+        gen_planes_at(p, yrow[2 * k + h], xw[k], xw[k], t, pl);
+        row_rand(pl, p, rr[k][h]);
+      }
+    }
+    const uint32_t perm = class_order(p.k0, p.k1, t);
+    __syncthreads();  // staging or the previous sweep complete
+#pragma unroll 1
+    for (int ph = 0; ph < 8; ++ph) {
+      const uint32_t cls = (perm >> (4 * ph)) & 0xFu;
+      const int a = (int)(cls >> 1);
+      if (cls & 1u) count += cyc_phase<C, KU, 1>(S, p, base0, yrow, xw, okm, rr, ur, uw, a, t);
+      else count += cyc_phase<C, KU, 0>(S, p, base0, yrow, xw, okm, rr, ur, uw, a, t);
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < R * C; i += blockDim.x) {
+    const int y = i / C, x = i - y * C;
+    store_word<LAYOUT>(p, y, 32 * x, S[(y + 2) * ST + x + 1], 32);
+  }
+  return count;
+}
+
+template <int LAYOUT, int C, int KU>
+__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p) {
+  extern __shared__ uint32_t S[];
+  constexpr int ST = CycGeom<C>::ST;
+  const unsigned count = cyc_sweeps<LAYOUT, C, KU>(S, p);
+  unsigned c = count;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  unsigned* red = reinterpret_cast<unsigned*>(S + (p.R + 4) * ST);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
+    p.accepted[0] += tot;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream) {
   const int tiles_y = (p.L + p.th - 1) / p.th;
   const dim3 grid(p.tiles_x * tiles_y), block(threads);
   const size_t lds = (size_t)p.R * (p.C + 2) * sizeof(uint32_t) + 16 * sizeof(unsigned);
+  if (cyclic && p.C >= 2 && p.C <= 11) {
+#define KK_CYC(LY, CC)                                                                            \
+  do {                                                                                            \
+    const size_t cl = ((size_t)(p.R + 4) * CycGeom<CC>::ST + 16) * sizeof(uint32_t);              \
+    if (ku == 1) hipLaunchKernelGGL((cyc_kernel<LY, CC, 1>), grid, block, cl, stream, p);         \
+    else hipLaunchKernelGGL((cyc_kernel<LY, CC, 2>), grid, block, cl, stream, p);                 \
+  } while (0)
+#define KK_CYC_C(LY)                                                                                          \
+  do {                                                                                                        \
+    switch (p.C) {                                                                                            \
+      case 2: KK_CYC(LY, 2); break;   case 3: KK_CYC(LY, 3); break;   case 4: KK_CYC(LY, 4); break;           \
+      case 5: KK_CYC(LY, 5); break;   case 6: KK_CYC(LY, 6); break;   case 7: KK_CYC(LY, 7); break;           \
+      case 8: KK_CYC(LY, 8); break;   case 9: KK_CYC(LY, 9); break;   case 10: KK_CYC(LY, 10); break;         \
+      default: KK_CYC(LY, 11); break;                                                                         \
+    }                                                                                                         \
+  } while (0)
+    if (layout == kLayoutBits) KK_CYC_C(kLayoutBits);
+    else KK_CYC_C(kLayoutInt8);
+#undef KK_CYC_C
+#undef KK_CYC
+    return hipGetLastError();
+  }
   if (!cyclic && (p.tww == 1 || p.tww == 2 || p.tww == 4 || p.tww == 8 || p.tww == 16)) {
 #define KK_HALO(LY, TW)                                                                                  \
   do {                                                                                                   \
