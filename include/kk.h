@@ -140,6 +140,41 @@ kk_status kk_sweep_timed(kk_sim *h, uint64_t n_sweeps, double *kernel_ms, uint64
 
 void kk_destroy(kk_sim *h);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent replicas (uneven L, composition, omega, seed)
+ * advanced together.  Replicas with L % 32 == 0 and 64 <= L <= 256 run in one
+ * persistent launch with the whole lattice held in LDS; the others run as
+ * one launch per sweep over all their tiles, replayed from a captured HIP
+ * graph.  A replica's result equals what kk_create_ex + kk_sweep gives for the
+ * same parameters (no replica or slot index enters any random number).
+ * ------------------------------------------------------------------------- */
+typedef struct kk_batch kk_batch;
+
+typedef struct {
+    uint32_t L;          /* side, as for kk_create */
+    uint32_t layout;     /* KK_LAYOUT_* */
+    double composition;  /* fraction of type 1, in [0, 1] */
+    double omega_kT;     /* interaction omega / kT, finite */
+    uint64_t seed;       /* Philox key */
+    uint64_t sweeps;     /* sweeps this replica makes on every kk_batch_run */
+} kk_replica;
+
+/* Create n replicas (each placed as kk_create would) on one device; hip_stream
+ * (NULL = own) carries the uploads and the tiled launches. */
+kk_status kk_batch_create(kk_batch **out, const kk_replica *reps, size_t n, void *hip_stream);
+
+/* Advance every replica by its `sweeps` and wait. */
+kk_status kk_batch_run(kk_batch *b);
+
+/* Borrow replica i's handle for queries (kk_get_lattice, kk_energy,
+ * kk_cluster_hist, kk_stats, ...).  The batch owns it: do not destroy it. */
+kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
+
+/* How the batch runs: resident replicas, tiled replicas, tile jobs per sweep. */
+kk_status kk_batch_info(kk_batch *b, size_t *n_resident, size_t *n_tiled, size_t *n_tile_jobs);
+
+void kk_batch_destroy(kk_batch *b);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *kk_last_error(void);
 

@@ -133,30 +133,6 @@ bool tile_valid(int L, const TileConfig& tc, std::string* why) {
 
 using namespace kk;
 
-struct kk_sim {
-  int L = 0;
-  int layout = 0;
-  double composition = 0, omega = 0;
-  uint64_t seed = 0;
-  uint32_t k0 = 0, k1 = 0;
-  uint64_t t = 0;
-  uint64_t attempts = 0;
-  void* lat[2] = {nullptr, nullptr};
-  int cur = 0;
-  unsigned long long* counters = nullptr;  // [0] unused, [1] energy scratch
-  unsigned long long* partials = nullptr;  // accepted moves, one running sum per sweep tile
-  size_t npartials = 0;
-  uint64_t accepted_base = 0;              // accepted moves folded in from earlier tile shapes
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-  uint64_t T[7] = {};
-  Accept acc{};
-  TileConfig tile{};
-  CclBuffers ccl{};
-  bool ccl_ready = false;
-  bool poisoned = false;
-};
 
 namespace {
 
@@ -383,6 +359,17 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
 }  // namespace
 
 namespace kk {
+kk_status device_alloc(void** p, size_t bytes) { return dmalloc(nullptr, p, bytes); }
+
+kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t n) {
+  if (n == 0) return KK_OK;
+  std::vector<unsigned long long> v(n);
+  KK_HIP(hipMemcpyAsync(v.data(), dev_counts, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  for (auto x : v) h->accepted_base += x;
+  return KK_OK;
+}
+
 uint64_t place_count(int L, double composition) {
   const double N = (double)L * (double)L;
   double v = std::floor(composition * N + 0.5);

@@ -1,0 +1,258 @@
+// kk_batch.cpp -- many independent lattices (replicas) of uneven size,
+// composition and omega advanced together on one GPU.
+//
+// Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <= 256)
+// are "resident": one persistent launch gives each its own workgroup, which
+// keeps the lattice in LDS for all of its sweeps.  The others are "tiled":
+// every sweep is one launch over all their halo tiles at once, and those
+// launches are captured in a HIP graph that is replayed.  Both run
+// concurrently on two streams.  No slot or replica index enters any random
+// counter, so every replica ends exactly where kk_sweep would have left it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/kk.h"
+#include "kk_host.hpp"
+#include "kk_kernels.hpp"
+
+using namespace kk;
+
+struct kk_batch {
+  std::vector<kk_sim*> sims;
+  std::vector<uint64_t> sweeps;
+  std::vector<int> resident, tiled;
+  std::vector<size_t> count_off, count_n;
+  size_t ncounts = 0;
+  hipStream_t sA = nullptr, sB = nullptr;
+  bool own_sB = false;
+  hipEvent_t ev_upload = nullptr, ev_done = nullptr;
+  SweepParams* d_params = nullptr;
+  void** d_bufs = nullptr;
+  unsigned long long* d_nsw = nullptr;
+  BatchTileJob* d_jobs = nullptr;
+  int njobs = 0;
+  int* d_res = nullptr;
+  size_t res_lds = 0;
+  unsigned* d_ctl = nullptr;
+  unsigned long long* d_counts = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_k = 0;
+  bool poisoned = false;
+};
+
+namespace {
+
+#define KB_HIP(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) {                                                                       \
+      b->poisoned = true;                                                                         \
+      return set_error(KK_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                                 \
+    }                                                                                             \
+  } while (0)
+
+bool is_resident(const kk_sim* h) { return h->L % 32 == 0 && h->L >= 64 && h->L <= 256; }
+
+void free_batch(kk_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* p : {(void*)b->d_params, (void*)b->d_bufs, (void*)b->d_nsw, (void*)b->d_jobs, (void*)b->d_res,
+                  (void*)b->d_ctl, (void*)b->d_counts})
+    if (p) (void)hipFree(p);
+  for (kk_sim* h : b->sims) kk_destroy(h);
+  if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
+  if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  if (b->sA) (void)hipStreamDestroy(b->sA);
+  if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
+}
+
+// Geometry of a replica's batch launch (resident: whole lattice; tiled: fixed tile).
+void batch_geometry(const kk_sim* h, bool resident, SweepParams* p) {
+  TileConfig tc;
+  if (resident) {
+    tc.cyclic = true;
+    tc.tww = h->L / 32;
+    tc.th = h->L;
+  } else {
+    tc.cyclic = false;
+    tc.tww = kBatchTww;
+    tc.th = std::min(kBatchTh, h->L);
+  }
+  tc.ku = 2;
+  tile_geometry(h->L, tc, p);
+  p->k0 = h->k0;
+  p->k1 = h->k1;
+  p->acc = h->acc;
+  p->layout = h->layout;
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void* hip_stream) {
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!reps || n == 0) return set_error(KK_EINVAL, "need at least one replica");
+  kk_batch* b = new (std::nothrow) kk_batch();
+  if (!b) return set_error(KK_ENOMEM, "host allocation failed");
+  auto fail = [&](kk_status st) {
+    free_batch(b);
+    delete b;
+    return st;
+  };
+  hipError_t e;
+  if (hip_stream) b->sB = static_cast<hipStream_t>(hip_stream);
+  else {
+    if ((e = hipStreamCreateWithFlags(&b->sB, hipStreamNonBlocking)) != hipSuccess)
+      return fail(set_error(KK_EDEVICE, "stream: %s", hipGetErrorString(e)));
+    b->own_sB = true;
+  }
+  if ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming)) != hipSuccess)
+    return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = nullptr;
+    kk_status st = kk_create_ex(&h, reps[i].L, reps[i].composition, reps[i].omega_kT, reps[i].seed, reps[i].layout,
+                                b->sB);
+    if (st != KK_OK) return fail(st);
+    b->sims.push_back(h);
+    b->sweeps.push_back(reps[i].sweeps);
+  }
+  // plan: resident replicas and the tile jobs of the others
+  std::vector<BatchTileJob> jobs;
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = b->sims[i];
+    const bool res = is_resident(h);
+    SweepParams p{};
+    batch_geometry(h, res, &p);
+    const size_t tiles = res ? 1 : (size_t)p.tiles_x * (size_t)((h->L + p.th - 1) / p.th);
+    b->count_off.push_back(b->ncounts);
+    b->count_n.push_back(tiles);
+    b->ncounts += tiles;
+    if (res) {
+      b->resident.push_back((int)i);
+      b->res_lds = std::max(b->res_lds, batch_resident_lds_bytes(h->L));
+    } else {
+      b->tiled.push_back((int)i);
+      for (size_t t = 0; t < tiles; ++t) jobs.push_back(BatchTileJob{(int)i, (int)t});
+    }
+  }
+  b->njobs = (int)jobs.size();
+  kk_status st = KK_OK;
+  if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_bufs, 2 * n * sizeof(void*));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_nsw, n * sizeof(unsigned long long));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_counts, b->ncounts * sizeof(unsigned long long));
+  if (st == KK_OK && b->njobs) st = device_alloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchTileJob));
+  if (st == KK_OK && !b->resident.empty()) st = device_alloc((void**)&b->d_res, b->resident.size() * sizeof(int));
+  if (st != KK_OK) return fail(st);
+  if (b->njobs && (e = hipMemcpy(b->d_jobs, jobs.data(), jobs.size() * sizeof(BatchTileJob),
+                                 hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(set_error(KK_EDEVICE, "upload jobs: %s", hipGetErrorString(e)));
+  if (!b->resident.empty() && (e = hipMemcpy(b->d_res, b->resident.data(), b->resident.size() * sizeof(int),
+                                             hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(set_error(KK_EDEVICE, "upload ids: %s", hipGetErrorString(e)));
+  // one captured graph of sweep launches over every tile job
+  if (b->njobs) {
+    uint64_t maxsw = 0;
+    for (int i : b->tiled) maxsw = std::max(maxsw, b->sweeps[i]);
+    b->graph_k = (int)std::max<uint64_t>(1, std::min<uint64_t>(maxsw, 64));
+    if ((e = hipStreamBeginCapture(b->sB, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return fail(set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e)));
+    for (int k = 0; k < b->graph_k; ++k)
+      (void)launch_batch_tiles(b->d_params, b->d_bufs, b->d_nsw, b->d_jobs, b->njobs, b->d_ctl, b->sB);
+    e = hipStreamEndCapture(b->sB, &b->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(set_error(KK_EDEVICE, "graph: %s", hipGetErrorString(e)));
+  }
+  *out = b;
+  return KK_OK;
+}
+
+kk_status kk_batch_run(kk_batch* b) {
+  if (!b) return set_error(KK_EINVAL, "NULL batch");
+  if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  const size_t n = b->sims.size();
+  std::vector<SweepParams> params(n);
+  std::vector<void*> bufs(2 * n);
+  std::vector<unsigned long long> nsw(n);
+  uint64_t maxsw = 0;
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = b->sims[i];
+    if (h->poisoned) return set_error(KK_ESTATE, "replica %zu poisoned", i);
+    if (h->t + b->sweeps[i] >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "sweep counter overflow");
+    const bool res = is_resident(h);
+    SweepParams& p = params[i];
+    batch_geometry(h, res, &p);
+    p.t0 = h->t;
+    p.accepted = b->d_counts + b->count_off[i];
+    bufs[2 * i] = h->lat[h->cur];
+    bufs[2 * i + 1] = h->lat[h->cur ^ 1];
+    p.src = p.dst = h->lat[h->cur];
+    p.nsweeps = (int)b->sweeps[i];
+    nsw[i] = b->sweeps[i];
+    if (!res) maxsw = std::max(maxsw, b->sweeps[i]);
+  }
+  for (int i : b->resident)
+    if (b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per run");
+  KB_HIP(hipMemcpyAsync(b->d_params, params.data(), n * sizeof(SweepParams), hipMemcpyHostToDevice, b->sB));
+  KB_HIP(hipMemcpyAsync(b->d_bufs, bufs.data(), 2 * n * sizeof(void*), hipMemcpyHostToDevice, b->sB));
+  KB_HIP(hipMemcpyAsync(b->d_nsw, nsw.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice, b->sB));
+  KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
+  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned), b->sB));
+  KB_HIP(hipEventRecord(b->ev_upload, b->sB));
+  if (!b->resident.empty()) {
+    KB_HIP(hipStreamWaitEvent(b->sA, b->ev_upload, 0));
+    KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->resident.size(), b->res_lds, b->sA));
+  }
+  if (b->njobs && maxsw) {
+    const uint64_t reps = (maxsw + b->graph_k - 1) / b->graph_k;
+    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->gexec, b->sB));
+  }
+  KB_HIP(hipEventRecord(b->ev_done, b->sA));
+  KB_HIP(hipStreamWaitEvent(b->sB, b->ev_done, 0));
+  KB_HIP(hipStreamSynchronize(b->sB));
+  std::vector<unsigned long long> counts(b->ncounts);
+  KB_HIP(hipMemcpy(counts.data(), b->d_counts, b->ncounts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = b->sims[i];
+    for (size_t k = 0; k < b->count_n[i]; ++k) h->accepted_base += counts[b->count_off[i] + k];
+    h->t += b->sweeps[i];
+    h->attempts += b->sweeps[i] * (uint64_t)h->L * (uint64_t)h->L;
+    if (!is_resident(h)) h->cur ^= (int)(b->sweeps[i] & 1u);
+  }
+  return KK_OK;
+}
+
+kk_status kk_batch_sim(kk_batch* b, size_t i, kk_sim** sim_out) {
+  if (!b || !sim_out) return set_error(KK_EINVAL, "NULL argument");
+  if (i >= b->sims.size()) return set_error(KK_EINVAL, "replica %zu out of range (%zu)", i, b->sims.size());
+  *sim_out = b->sims[i];
+  return KK_OK;
+}
+
+kk_status kk_batch_info(kk_batch* b, size_t* n_resident, size_t* n_tiled, size_t* n_tile_jobs) {
+  if (!b) return set_error(KK_EINVAL, "NULL batch");
+  if (n_resident) *n_resident = b->resident.size();
+  if (n_tiled) *n_tiled = b->tiled.size();
+  if (n_tile_jobs) *n_tile_jobs = (size_t)b->njobs;
+  return KK_OK;
+}
+
+void kk_batch_destroy(kk_batch* b) {
+  if (!b) return;
+  if (b->sB) (void)hipStreamSynchronize(b->sB);
+  if (b->sA) (void)hipStreamSynchronize(b->sA);
+  free_batch(b);
+  delete b;
+}
+
+}  // extern "C"

@@ -27,3 +27,35 @@ int tile_geometry(int L, const TileConfig& tc, SweepParams* p);
 bool tile_valid(int L, const TileConfig& tc, std::string* why);
 
 }  // namespace kk
+
+// A simulation handle (the opaque kk_sim of kk.h).
+struct kk_sim {
+  int L = 0;
+  int layout = 0;
+  double composition = 0, omega = 0;
+  uint64_t seed = 0;
+  uint32_t k0 = 0, k1 = 0;
+  uint64_t t = 0;
+  uint64_t attempts = 0;
+  void* lat[2] = {nullptr, nullptr};
+  int cur = 0;
+  unsigned long long* counters = nullptr;  // [0] unused, [1] energy scratch
+  unsigned long long* partials = nullptr;  // accepted moves, one running sum per sweep tile
+  size_t npartials = 0;
+  uint64_t accepted_base = 0;              // accepted moves folded in from earlier tile shapes
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  uint64_t T[7] = {};
+  kk::Accept acc{};
+  kk::TileConfig tile{};
+  kk::CclBuffers ccl{};
+  bool ccl_ready = false;
+  bool poisoned = false;
+};
+
+namespace kk {
+// helpers shared with the batch engine (kk_api.cpp)
+kk_status device_alloc(void** p, size_t bytes);
+kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t n);
+}  // namespace kk

@@ -22,12 +22,28 @@ struct SweepParams {
   int C, R;                  // LDS words per row, rows (tile + halo)
   int row0, npairs, nunits;  // first computed LDS row, computed row pairs, units = pairs * C
   int nsweeps;               // sweeps in this launch
+  int layout;                // kLayoutInt8 or kLayoutBits (read by the batch kernels)
   uint32_t k0, k1;           // Philox key (seed)
   uint64_t t0;               // first sweep index
   Accept acc;
 };
 
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream);
+
+// Batch kernels.  Tiled replicas: one workgroup per (replica, tile) job and one
+// launch per sweep; the sweep index lives in ctl[0] and the last workgroup to
+// finish advances it (ctl[1] counts finished workgroups), so a captured
+// graph of launches can be replayed.  Resident replicas: one workgroup per
+// replica running all of its sweeps with the whole lattice in LDS.
+constexpr int kBatchTww = 8, kBatchTh = 128, kBatchThreads = 512;
+struct BatchTileJob {
+  int rep, tile;
+};
+hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const unsigned long long* nsw,
+                              const BatchTileJob* jobs, int njobs, unsigned* ctl, hipStream_t stream);
+hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, hipStream_t stream);
+size_t batch_tile_lds_bytes();
+size_t batch_resident_lds_bytes(int L);
 
 // N_AB (unlike nearest-neighbour bonds) added into *out.
 hipError_t launch_energy(const void* lat, int layout, int L, unsigned long long* out, hipStream_t stream);

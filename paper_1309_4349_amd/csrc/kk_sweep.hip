@@ -568,14 +568,14 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
 // the neighbourhoods of all its units before issuing any exchange (the
 // conflict-free schedule makes that reordering exact), so the LDS latency of
 // the second unit hides behind the first.
+// One sweep of tile `tile` of the lattice described by p (halo mode).
+// Returns this thread's accepted count for the tile interior.
 template <int LAYOUT, int TWW, int KU>
-__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams p) {
+__device__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
   constexpr int C = HaloGeom<TWW>::C;
   constexpr int ST = HaloGeom<TWW>::ST;
   constexpr int CP = C + 2;   // staged words per row (the pads included)
   constexpr int NSTG = 6;     // staged global words per thread
-  extern __shared__ uint32_t S[];
-  const int tile = blockIdx.x;
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
   const int X0 = tx * TWW * 32, Y0 = ty * p.th;
   const int XL = X0 - 32, YT = Y0 - 16;
@@ -669,18 +669,29 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams 
     store_word<LAYOUT>(p, Y0 + rr2, x0, nb == 32 ? val : (val & ((1u << nb) - 1u)), nb);
   }
 
+  return count;
+}
+
+// Block-wide sum of the per-thread accepted counts, added to *dst by thread 0.
+__device__ __forceinline__ void add_block_count(uint32_t* red_lds, unsigned count, unsigned long long* dst) {
   unsigned c = count;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-  unsigned* red = reinterpret_cast<unsigned*>(S + p.R * ST);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red_lds[threadIdx.x >> 6] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long tot = 0;
-    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
-    p.accepted[tile] += tot;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red_lds[wv];
+    *dst += tot;
   }
 }
 
+template <int LAYOUT, int TWW, int KU>
+__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams p) {
+  extern __shared__ uint32_t S[];
+  const unsigned count = halo_tile_sweep<LAYOUT, TWW, KU>(S, p, blockIdx.x);
+  add_block_count(S + p.R * HaloGeom<TWW>::ST, count, p.accepted + blockIdx.x);
+}
 
 // ---------------------------------------------------------------------------
 // Cyclic whole-lattice tile (L % 32 == 0, C = L/32 words per row).  The
@@ -839,19 +850,62 @@ __device__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
 template <int LAYOUT, int C, int KU>
 __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p) {
   extern __shared__ uint32_t S[];
-  constexpr int ST = CycGeom<C>::ST;
   const unsigned count = cyc_sweeps<LAYOUT, C, KU>(S, p);
-  unsigned c = count;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-  unsigned* red = reinterpret_cast<unsigned*>(S + (p.R + 4) * ST);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long tot = 0;
-    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
-    p.accepted[0] += tot;
+  add_block_count(S + (p.R + 4) * CycGeom<C>::ST, count, p.accepted);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batch kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepParams* reps, void* const* bufs,
+                                                                   const unsigned long long* nsw,
+                                                                   const BatchTileJob* jobs, unsigned* ctl) {
+  extern __shared__ uint32_t S[];
+  const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const BatchTileJob job = jobs[blockIdx.x];
+  if (s < nsw[job.rep]) {
+    SweepParams p = reps[job.rep];
+    p.src = bufs[2 * job.rep + (s & 1u)];
+    p.dst = bufs[2 * job.rep + ((s + 1u) & 1u)];
+    p.t0 += s;
+    unsigned count;
+    if (p.layout == kLayoutBits) count = halo_tile_sweep<kLayoutBits, kBatchTww, 2>(S, p, job.tile);
+    else count = halo_tile_sweep<kLayoutInt8, kBatchTww, 2>(S, p, job.tile);
+    add_block_count(S + p.R * HaloGeom<kBatchTww>::ST, count, p.accepted + job.tile);
   }
+  // the last workgroup to finish advances the sweep index for the next launch
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&ctl[1], 1u);
+    if (prev == gridDim.x - 1) {
+      ctl[1] = 0u;
+      ctl[0] = s + 1u;
+      __threadfence();
+    }
+  }
+}
+
+template <int LAYOUT>
+__device__ unsigned resident_dispatch(uint32_t* S, const SweepParams& p) {
+  switch (p.C) {
+    case 2: return cyc_sweeps<LAYOUT, 2, 2>(S, p);
+    case 3: return cyc_sweeps<LAYOUT, 3, 2>(S, p);
+    case 4: return cyc_sweeps<LAYOUT, 4, 2>(S, p);
+    case 5: return cyc_sweeps<LAYOUT, 5, 2>(S, p);
+    case 6: return cyc_sweeps<LAYOUT, 6, 2>(S, p);
+    case 7: return cyc_sweeps<LAYOUT, 7, 2>(S, p);
+    default: return cyc_sweeps<LAYOUT, 8, 2>(S, p);
+  }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void batch_resident_kernel(const SweepParams* reps, const int* ids) {
+  extern __shared__ uint32_t S[];
+  const SweepParams p = reps[ids[blockIdx.x]];
+  const unsigned count = (p.layout == kLayoutBits) ? resident_dispatch<kLayoutBits>(S, p)
+                                                   : resident_dispatch<kLayoutInt8>(S, p);
+  // the reduction area sits past the largest resident tile (rows L+4, stride <= 36)
+  add_block_count(S + (p.R + 4) * 36, count, p.accepted);
 }
 
 }  // namespace
@@ -914,6 +968,30 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
     else { if (ku == 1) KK_LAUNCH(kLayoutInt8, false, 1); else KK_LAUNCH(kLayoutInt8, false, 2); }
   }
 #undef KK_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace kk
+
+namespace kk {
+
+size_t batch_tile_lds_bytes() {
+  const int R = kBatchTh + 32;
+  return ((size_t)R * HaloGeom<kBatchTww>::ST + 16 + R + HaloGeom<kBatchTww>::C) * sizeof(uint32_t);
+}
+
+size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * sizeof(uint32_t); }
+
+hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const unsigned long long* nsw,
+                              const BatchTileJob* jobs, int njobs, unsigned* ctl, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchThreads), batch_tile_lds_bytes(), stream, reps, bufs,
+                     nsw, jobs, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL(batch_resident_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ EXPORTS = [
     "kk_create", "kk_create_ex", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
+    "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_destroy",
 ]
 
 
@@ -34,6 +35,11 @@ class KKError(RuntimeError):
 
 class HistEntry(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint64), ("count", ctypes.c_uint64)]
+
+
+class Replica(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("composition", ctypes.c_double),
+                ("omega_kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64)]
 
 
 _lib = None
@@ -71,6 +77,10 @@ def load(path: str = LIB_PATH):
         "kk_get_tile": [P, u32p, u32p, u32p],
         "kk_stream": [P, PP],
         "kk_sweep_timed": [P, U64, dp, u64p],
+        "kk_batch_create": [PP, ctypes.POINTER(Replica), ctypes.c_size_t, P],
+        "kk_batch_run": [P],
+        "kk_batch_sim": [P, ctypes.c_size_t, PP],
+        "kk_batch_info": [P, szp, szp, szp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -78,6 +88,8 @@ def load(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.kk_destroy.argtypes = [P]
     lib.kk_destroy.restype = None
+    lib.kk_batch_destroy.argtypes = [P]
+    lib.kk_batch_destroy.restype = None
     lib.kk_last_error.argtypes = []
     lib.kk_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -190,3 +202,57 @@ class Sim:
         p = ctypes.c_void_p()
         _check(load().kk_stream(self._h, ctypes.byref(p)))
         return p.value or 0
+
+
+class _Borrowed(Sim):
+    """A replica handle owned by a Batch (never destroyed from Python)."""
+
+    def __init__(self, handle, L, omega, seed):
+        self._h = handle
+        self.L = L
+        self.omega = omega
+        self.seed = seed
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """Many replicas advanced together (kk_batch_*).  `jobs` are objects with
+    L, composition, omega, seed, sweeps and layout attributes."""
+
+    def __init__(self, jobs, stream: Optional[int] = None):
+        lib = load()
+        arr = (Replica * len(jobs))()
+        for i, j in enumerate(jobs):
+            arr[i] = Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
+                             j.seed & (2**64 - 1), int(j.sweeps))
+        h = ctypes.c_void_p()
+        _check(lib.kk_batch_create(ctypes.byref(h), arr, len(jobs), ctypes.c_void_p(stream) if stream else None))
+        self._h = h
+        self.jobs = list(jobs)
+
+    def run(self):
+        _check(load().kk_batch_run(self._h))
+
+    def sim(self, i: int) -> Sim:
+        h = ctypes.c_void_p()
+        _check(load().kk_batch_sim(self._h, i, ctypes.byref(h)))
+        j = self.jobs[i]
+        return _Borrowed(h, j.L, float(j.omega), j.seed)
+
+    def info(self):
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().kk_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"resident": a.value, "tiled": b.value, "tile_jobs": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().kk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,18 +86,14 @@ def big_4096(sweeps: int = 10_000) -> Job:
 def batch_replicas(n: int = 256, sweeps: int = 10_000, seed: int = MASTER_SEED ^ 3) -> List[Job]:
     """Replica table: L = 64 * 16**U (log-uniform 64..1024), x ~ U[0.2,0.8], omega ~ U[0.2,1.4].
 
-    Replicas with L_raw >= 256 are rounded to a multiple of 32 and bit-packed,
-    the rest to a multiple of 4 and stored as int8."""
+    Every L is rounded to a multiple of 32 (whole 32-site words per row);
+    replicas with L_raw >= 256 are bit-packed, the rest stored as int8."""
     rng = np.random.default_rng(seed)
     jobs = []
     for i in range(n):
         raw = 64.0 * 16.0 ** rng.random()
-        if raw >= 256.0:
-            L = int(round(raw / 32.0)) * 32
-            layout = "bitpacked"
-        else:
-            L = int(round(raw / 4.0)) * 4
-            layout = "int8"
+        L = int(round(raw / 32.0)) * 32
+        layout = "bitpacked" if raw >= 256.0 else "int8"
         L = max(64, min(1024, L))
         x = float(rng.uniform(0.2, 0.8))
         w = float(rng.uniform(0.2, 1.4))

@@ -1,0 +1,79 @@
+"""GPU: batched replicas equal the same replicas run alone, bit for bit.
+
+The batch mixes resident (whole lattice in LDS) and tiled replicas, int8 and
+bit-packed, positive, negative and zero omega, and uneven sweep counts."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_4349_amd import kk
+from paper_1309_4349_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_jobs():
+    specs = [(64, "int8", 0.5, 0.5, 30), (96, "bitpacked", 0.3, 1.2, 17), (128, "int8", 0.7, -0.4, 25),
+             (160, "bitpacked", 0.45, 0.0, 9), (224, "int8", 0.5, 0.88, 12), (256, "bitpacked", 0.2, 1.4, 21),
+             (100, "int8", 0.6, 0.9, 14), (288, "bitpacked", 0.5, 0.6, 11), (320, "int8", 0.35, 1.1, 8),
+             (512, "bitpacked", 0.5, 0.88, 6), (68, "int8", 0.4, 0.3, 19), (608, "bitpacked", 0.25, 1.3, 5)]
+    jobs = []
+    for i, (L, lay, x, w, n) in enumerate(specs):
+        jobs.append(wl.Job(L=L, composition=x, omega=w, seed=wl.job_seed(77, i), sweeps=n, layout=lay))
+    return jobs
+
+
+def test_batch_equals_alone_bitexact():
+    jobs = mixed_jobs()
+    say("case batch of", len(jobs), "mixed replicas")
+    b = kk.Batch(jobs)
+    info = b.info()
+    assert info["resident"] >= 5 and info["tiled"] >= 4
+    b.run()
+    b.run()   # a second run continues from the first
+    for i, j in enumerate(jobs):
+        say(f"  replica {i}: L={j.L} {j.layout} x={j.composition} omega={j.omega} sweeps=2x{j.sweeps}")
+        alone = kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout)
+        alone.sweep(2 * j.sweeps)
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), alone.get_lattice())
+        assert s.stats() == alone.stats()
+        assert s.energy() == alone.energy()
+        alone.close()
+    b.close()
+
+
+def test_batch_matches_oracle_small():
+    jobs = [wl.Job(L=64, composition=0.5, omega=0.7, seed=5, sweeps=40, layout="bitpacked"),
+            wl.Job(L=132, composition=0.3, omega=1.0, seed=6, sweeps=7, layout="int8")]
+    b = kk.Batch(jobs)
+    b.run()
+    for i, j in enumerate(jobs):
+        ref = oracle.init(j.L, j.composition, j.seed)
+        acc = oracle.sweeps(ref, j.omega, j.seed, 0, j.sweeps)
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), ref)
+        assert s.stats()[2] == acc
+        assert s.cluster_hist(1) == oracle.cluster_hist(ref, 1)
+    b.close()
+
+
+def test_batch_standing_replica_table_prefix():
+    jobs = wl.batch_replicas(n=256, sweeps=3)
+    say("case 256-replica table, 3 sweeps each")
+    b = kk.Batch(jobs)
+    b.run()
+    for i in range(0, 256, 37):
+        j = jobs[i]
+        alone = kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout)
+        alone.sweep(j.sweeps)
+        assert np.array_equal(b.sim(i).get_lattice(), alone.get_lattice()), i
+        alone.close()
+    b.close()
