@@ -64,6 +64,47 @@ def cpu_baseline(job, budget_s: float = 12.0):
                       f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})"}
 
 
+def batched_vs_plain(sweeps: int, plain_sweeps: int):
+    """Aggregate attempts/s of the 256-replica table: one batch run against the
+    same replicas advanced one after another through the plain path."""
+    import torch
+
+    from paper_1309_4349_amd import kk
+    from paper_1309_4349_amd import workloads as wl
+
+    jobs = wl.batch_replicas(n=256, sweeps=sweeps)
+    sites = sum(j.L * j.L for j in jobs)
+    b = kk.Batch(jobs)
+    info = b.info()
+    b.run()   # warm-up run (also compiles nothing: the library is prebuilt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    batched_rate = sites * sweeps / tb
+    log(f"[bench] batch: {len(jobs)} replicas x {sweeps} sweeps in {tb:.3f} s = {batched_rate:.3e} attempts/s {info}")
+    b.close()
+    sims = [kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout) for j in jobs]
+    for s in sims:
+        s.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.sweep(plain_sweeps)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    plain_rate = sites * plain_sweeps / tp
+    log(f"[bench] plain: {len(jobs)} replicas one at a time x {plain_sweeps} sweeps in {tp:.3f} s = "
+        f"{plain_rate:.3e} attempts/s")
+    for s in sims:
+        s.close()
+    return {"workload": "256 replicas, L log-uniform 64..1024 (multiples of 32), x~U[0.2,0.8], omega~U[0.2,1.4]",
+            "sites": sites, "batched_sweeps": sweeps, "batched_attempts_per_s": batched_rate,
+            "batched_s": tb, "plain_sweeps_per_replica": plain_sweeps, "plain_attempts_per_s": plain_rate,
+            "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +113,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=10_000, help="sweeps per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-sweeps", type=int, default=10_000, help="sweeps per replica in the batch run")
+    ap.add_argument("--batch-plain-sweeps", type=int, default=500,
+                    help="sweeps per replica for the one-at-a-time plain baseline")
     ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
@@ -145,11 +189,7 @@ def main():
 
     batched = None
     if not args.no_batch:
-        try:
-            from paper_1309_4349_amd import batch as kb
-            batched = kb.bench_batched_vs_plain(log=log)
-        except ImportError:
-            batched = None
+        batched = batched_vs_plain(args.batch_sweeps, args.batch_plain_sweeps)
 
     cpu = None
     if not args.no_cpu:

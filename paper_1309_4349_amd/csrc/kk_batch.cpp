@@ -1,12 +1,15 @@
 // kk_batch.cpp -- many independent lattices (replicas) of uneven size,
 // composition and omega advanced together on one GPU.
 //
-// Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <= 256)
+// Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <= 288)
 // are "resident": one persistent launch gives each its own workgroup, which
 // keeps the lattice in LDS for all of its sweeps.  The others are "tiled":
-// every sweep is one launch over all their halo tiles at once, and those
-// launches are captured in a HIP graph that is replayed.  Both run
-// concurrently on two streams.  No slot or replica index enters any random
+// they are split into a few groups of equal work; for each group every sweep
+// is one launch over all of the group's halo tiles, and those launches are
+// captured in a HIP graph that is replayed.  The resident launch and the
+// groups run concurrently, each on its own stream (few streams in all: the
+// device multiplexes streams over a small number of hardware queues, and two
+// streams sharing one queue serialise).  No slot or replica index enters any random
 // counter, so every replica ends exactly where kk_sweep would have left it.
 #include <hip/hip_runtime.h>
 
@@ -28,18 +31,25 @@ struct kk_batch {
   size_t ncounts = 0;
   hipStream_t sA = nullptr, sB = nullptr;
   bool own_sB = false;
-  hipEvent_t ev_upload = nullptr, ev_done = nullptr;
+  hipEvent_t ev_upload = nullptr, ev_done = nullptr, ev_res = nullptr;
   SweepParams* d_params = nullptr;
   void** d_bufs = nullptr;
   unsigned long long* d_nsw = nullptr;
   BatchTileJob* d_jobs = nullptr;
   int njobs = 0;
+  // tiled replicas split into work-balanced groups, each with its own stream,
+  // sweep counter and captured graph, so that the groups' launches overlap
+  std::vector<int> tg_off, tg_n;
+  std::vector<int> job_rep;  // host copy: replica of every tile job
+  std::vector<uint64_t> tg_maxsw;
+  std::vector<hipStream_t> tg_stream;
+  std::vector<hipGraph_t> tg_graph;
+  std::vector<hipGraphExec_t> tg_exec;
+  std::vector<hipEvent_t> tg_done;
   int* d_res = nullptr;
   size_t res_lds = 0;
   unsigned* d_ctl = nullptr;
   unsigned long long* d_counts = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
   int graph_k = 0;
   bool poisoned = false;
 };
@@ -56,15 +66,20 @@ namespace {
     }                                                                                             \
   } while (0)
 
-bool is_resident(const kk_sim* h) { return h->L % 32 == 0 && h->L >= 64 && h->L <= 256; }
+int jobs_rep(const kk_batch* b, int q) { return b->job_rep[q]; }
+
+bool is_resident(const kk_sim* h) { return h->L % 32 == 0 && h->L >= 64 && h->L / 32 <= kResidentMaxC; }
 
 void free_batch(kk_batch* b) {
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipGraphExec_t ge : b->tg_exec) (void)hipGraphExecDestroy(ge);
+  for (hipGraph_t g : b->tg_graph) (void)hipGraphDestroy(g);
+  for (hipStream_t st : b->tg_stream) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->tg_done) (void)hipEventDestroy(ev);
   for (void* p : {(void*)b->d_params, (void*)b->d_bufs, (void*)b->d_nsw, (void*)b->d_jobs, (void*)b->d_res,
                   (void*)b->d_ctl, (void*)b->d_counts})
     if (p) (void)hipFree(p);
   for (kk_sim* h : b->sims) kk_destroy(h);
+  if (b->ev_res) (void)hipEventDestroy(b->ev_res);
   if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
   if (b->ev_done) (void)hipEventDestroy(b->ev_done);
   if (b->sA) (void)hipStreamDestroy(b->sA);
@@ -79,9 +94,14 @@ void batch_geometry(const kk_sim* h, bool resident, SweepParams* p) {
     tc.tww = h->L / 32;
     tc.th = h->L;
   } else {
+    // tiles that cover the lattice exactly: balanced widths of at most
+    // kBatchMaxTww words and balanced heights of at most kBatchTh rows
+    const int W = (h->L + 31) / 32;
+    const int tx = (W + kBatchMaxTww - 1) / kBatchMaxTww;
+    const int ty = (h->L + kBatchTh - 1) / kBatchTh;
     tc.cyclic = false;
-    tc.tww = kBatchTww;
-    tc.th = std::min(kBatchTh, h->L);
+    tc.tww = (W + tx - 1) / tx;
+    tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
   }
   tc.ku = 2;
   tile_geometry(h->L, tc, p);
@@ -113,8 +133,7 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
       return fail(set_error(KK_EDEVICE, "stream: %s", hipGetErrorString(e)));
     b->own_sB = true;
   }
-  if ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
+  if ((e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming)) != hipSuccess)
     return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
   for (size_t i = 0; i < n; ++i) {
@@ -141,15 +160,46 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
       b->res_lds = std::max(b->res_lds, batch_resident_lds_bytes(h->L));
     } else {
       b->tiled.push_back((int)i);
-      for (size_t t = 0; t < tiles; ++t) jobs.push_back(BatchTileJob{(int)i, (int)t});
     }
   }
+  // LPT split of the tiled replicas into groups by work per sweep
+  const int ngroups = (int)std::min<size_t>(b->resident.empty() ? 4 : 3, b->tiled.size());
+  std::vector<std::vector<int>> groups(ngroups);
+  {
+    std::vector<int> order = b->tiled;
+    auto work = [&](int i) { return (double)b->sims[i]->L * b->sims[i]->L * (double)b->sweeps[i]; };
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+    std::vector<double> load(ngroups, 0.0);
+    for (int i : order) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      groups[g].push_back(i);
+      load[g] += work(i);
+    }
+  }
+  for (int g = 0; g < ngroups; ++g) {
+    b->tg_off.push_back((int)jobs.size());
+    uint64_t mx = 0;
+    for (int i : groups[g]) {
+      for (size_t t = 0; t < b->count_n[i]; ++t) jobs.push_back(BatchTileJob{i, (int)t});
+      mx = std::max(mx, b->sweeps[i]);
+    }
+    b->tg_n.push_back((int)jobs.size() - b->tg_off.back());
+    b->tg_maxsw.push_back(mx);
+  }
   b->njobs = (int)jobs.size();
+  for (const BatchTileJob& j : jobs) b->job_rep.push_back(j.rep);
+  // resident replicas: one launch, widest lattices first (they run longest)
+  std::stable_sort(b->resident.begin(), b->resident.end(),
+                   [&](int a, int c) { return b->sims[a]->L > b->sims[c]->L; });
+  if (!b->resident.empty() &&
+      ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
+       (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess))
+    return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
   kk_status st = KK_OK;
   if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
   if (st == KK_OK) st = device_alloc((void**)&b->d_bufs, 2 * n * sizeof(void*));
   if (st == KK_OK) st = device_alloc((void**)&b->d_nsw, n * sizeof(unsigned long long));
-  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * std::max<size_t>(1, b->tg_n.size()));
   if (st == KK_OK) st = device_alloc((void**)&b->d_counts, b->ncounts * sizeof(unsigned long long));
   if (st == KK_OK && b->njobs) st = device_alloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchTileJob));
   if (st == KK_OK && !b->resident.empty()) st = device_alloc((void**)&b->d_res, b->resident.size() * sizeof(int));
@@ -160,17 +210,33 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
   if (!b->resident.empty() && (e = hipMemcpy(b->d_res, b->resident.data(), b->resident.size() * sizeof(int),
                                              hipMemcpyHostToDevice)) != hipSuccess)
     return fail(set_error(KK_EDEVICE, "upload ids: %s", hipGetErrorString(e)));
-  // one captured graph of sweep launches over every tile job
-  if (b->njobs) {
-    uint64_t maxsw = 0;
-    for (int i : b->tiled) maxsw = std::max(maxsw, b->sweeps[i]);
-    b->graph_k = (int)std::max<uint64_t>(1, std::min<uint64_t>(maxsw, 64));
-    if ((e = hipStreamBeginCapture(b->sB, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+  // per group: a captured graph of graph_k sweep launches over the group's tile jobs
+  for (size_t g = 0; g < b->tg_n.size(); ++g) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
+    b->tg_stream.push_back(st);
+    b->tg_done.push_back(ev);
+    if (b->tg_n[g] == 0) {
+      b->tg_graph.push_back(nullptr);
+      b->tg_exec.push_back(nullptr);
+      continue;
+    }
+    const int k = (int)std::max<uint64_t>(1, std::min<uint64_t>(b->tg_maxsw[g], 64));
+    b->graph_k = std::max(b->graph_k, k);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return fail(set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e)));
-    for (int k = 0; k < b->graph_k; ++k)
-      (void)launch_batch_tiles(b->d_params, b->d_bufs, b->d_nsw, b->d_jobs, b->njobs, b->d_ctl, b->sB);
-    e = hipStreamEndCapture(b->sB, &b->graph);
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    for (int r = 0; r < k; ++r)
+      (void)launch_batch_tiles(b->d_params, b->d_bufs, b->d_nsw, b->d_jobs + b->tg_off[g], b->tg_n[g],
+                               b->d_ctl + 2 * g, st);
+    e = hipStreamEndCapture(st, &graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    b->tg_graph.push_back(graph);
+    b->tg_exec.push_back(exec);
     if (e != hipSuccess) return fail(set_error(KK_EDEVICE, "graph: %s", hipGetErrorString(e)));
   }
   *out = b;
@@ -184,7 +250,6 @@ kk_status kk_batch_run(kk_batch* b) {
   std::vector<SweepParams> params(n);
   std::vector<void*> bufs(2 * n);
   std::vector<unsigned long long> nsw(n);
-  uint64_t maxsw = 0;
   for (size_t i = 0; i < n; ++i) {
     kk_sim* h = b->sims[i];
     if (h->poisoned) return set_error(KK_ESTATE, "replica %zu poisoned", i);
@@ -199,7 +264,6 @@ kk_status kk_batch_run(kk_batch* b) {
     p.src = p.dst = h->lat[h->cur];
     p.nsweeps = (int)b->sweeps[i];
     nsw[i] = b->sweeps[i];
-    if (!res) maxsw = std::max(maxsw, b->sweeps[i]);
   }
   for (int i : b->resident)
     if (b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per run");
@@ -207,18 +271,26 @@ kk_status kk_batch_run(kk_batch* b) {
   KB_HIP(hipMemcpyAsync(b->d_bufs, bufs.data(), 2 * n * sizeof(void*), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemcpyAsync(b->d_nsw, nsw.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
-  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned), b->sB));
+  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * std::max<size_t>(1, b->tg_n.size()), b->sB));
   KB_HIP(hipEventRecord(b->ev_upload, b->sB));
   if (!b->resident.empty()) {
     KB_HIP(hipStreamWaitEvent(b->sA, b->ev_upload, 0));
     KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->resident.size(), b->res_lds, b->sA));
+    KB_HIP(hipEventRecord(b->ev_res, b->sA));
   }
-  if (b->njobs && maxsw) {
-    const uint64_t reps = (maxsw + b->graph_k - 1) / b->graph_k;
-    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->gexec, b->sB));
+  for (size_t g = 0; g < b->tg_n.size(); ++g) {
+    if (!b->tg_exec[g]) continue;
+    hipStream_t st = b->tg_stream[g];
+    KB_HIP(hipStreamWaitEvent(st, b->ev_upload, 0));
+    uint64_t mx = 0;
+    for (int q = b->tg_off[g]; q < b->tg_off[g] + b->tg_n[g]; ++q) mx = std::max<uint64_t>(mx, nsw[jobs_rep(b, q)]);
+    const int k = (int)std::max<uint64_t>(1, std::min<uint64_t>(b->tg_maxsw[g], 64));
+    const uint64_t reps = (mx + k - 1) / k;
+    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->tg_exec[g], st));
+    KB_HIP(hipEventRecord(b->tg_done[g], st));
   }
-  KB_HIP(hipEventRecord(b->ev_done, b->sA));
-  KB_HIP(hipStreamWaitEvent(b->sB, b->ev_done, 0));
+  if (!b->resident.empty()) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
+  for (hipEvent_t ev : b->tg_done) KB_HIP(hipStreamWaitEvent(b->sB, ev, 0));
   KB_HIP(hipStreamSynchronize(b->sB));
   std::vector<unsigned long long> counts(b->ncounts);
   KB_HIP(hipMemcpy(counts.data(), b->d_counts, b->ncounts * sizeof(unsigned long long), hipMemcpyDeviceToHost));

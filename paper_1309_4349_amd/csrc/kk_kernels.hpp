@@ -33,15 +33,18 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
 // Batch kernels.  Tiled replicas: one workgroup per (replica, tile) job and one
 // launch per sweep; the sweep index lives in ctl[0] and the last workgroup to
 // finish advances it (ctl[1] counts finished workgroups), so a captured
-// graph of launches can be replayed.  Resident replicas: one workgroup per
-// replica running all of its sweeps with the whole lattice in LDS.
-constexpr int kBatchTww = 8, kBatchTh = 128, kBatchThreads = 512;
+// graph of launches can be replayed.  Resident replicas (L % 32 == 0,
+// 2 <= L/32 <= kResidentMaxC): one launch, one workgroup per replica running
+// all of its sweeps with the whole lattice in LDS.
+constexpr int kBatchMaxTww = 16, kBatchTh = 128, kBatchThreads = 768;
 struct BatchTileJob {
   int rep, tile;
 };
 hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const unsigned long long* nsw,
                               const BatchTileJob* jobs, int njobs, unsigned* ctl, hipStream_t stream);
-hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
+                                 hipStream_t stream);
+constexpr int kResidentMaxC = 9;
 size_t batch_tile_lds_bytes();
 size_t batch_resident_lds_bytes(int L);
 

@@ -173,6 +173,25 @@ __device__ __forceinline__ uint32_t load_word_at(const SweepParams& p, int y, in
   return v;
 }
 
+// Layout chosen at run time (LAYOUT == 0) or at compile time.
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t load_word_any(const SweepParams& p, int y, int x0) {
+  if constexpr (LAYOUT == 0)
+    return p.layout == kLayoutBits ? load_word_at<kLayoutBits>(p, y, x0) : load_word_at<kLayoutInt8>(p, y, x0);
+  else
+    return load_word_at<LAYOUT>(p, y, x0);
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store_word_any(const SweepParams& p, int y, int x0, uint32_t v, int nbits) {
+  if constexpr (LAYOUT == 0) {
+    if (p.layout == kLayoutBits) store_word<kLayoutBits>(p, y, x0, v, nbits);
+    else store_word<kLayoutInt8>(p, y, x0, v, nbits);
+  } else {
+    store_word<LAYOUT>(p, y, x0, v, nbits);
+  }
+}
+
 // Random planes of the 32 sites starting at true column x0 of true row y.
 __device__ __forceinline__ void gen_planes_at(const SweepParams& p, int y, int x0, int Xw, uint64_t t, uint32_t* pl) {
   if ((x0 & 31) == 0 && x0 + 32 <= p.L) {
@@ -512,11 +531,10 @@ struct HaloGeom {
 // One phase of the halo kernel for the thread's units, active row = r0 + H.
 // Branch-free over the units: a unit beyond the tile reads a valid word and
 // has an empty centre mask, so it decides nothing and writes nothing.
-template <int TWW, int KU, int H>
+template <int ST, int KU, int H>
 __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p, const int* base0, const int* yrow,
                                                const int* xw, const uint32_t* okm, const RowRand (*rr)[2],
                                                const uint32_t (*imask)[2], int a, uint64_t t) {
-  constexpr int ST = HaloGeom<TWW>::ST;
   uint32_t v[KU][11];
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
@@ -570,16 +588,22 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
 // the second unit hides behind the first.
 // One sweep of tile `tile` of the lattice described by p (halo mode).
 // Returns this thread's accepted count for the tile interior.
+// TWW == 0 selects a runtime tile width (p.tww <= kFlexMaxTww) with a fixed
+// row stride, for tiles sized to fit a lattice exactly.
+constexpr int kFlexMaxTww = 16;
+constexpr int kFlexST = HaloGeom<kFlexMaxTww>::ST;
+
 template <int LAYOUT, int TWW, int KU>
-__device__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
-  constexpr int C = HaloGeom<TWW>::C;
-  constexpr int ST = HaloGeom<TWW>::ST;
-  constexpr int CP = C + 2;   // staged words per row (the pads included)
+__device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
+  const int C = TWW > 0 ? HaloGeom<(TWW > 0 ? TWW : 1)>::C : p.tww + 2;
+  constexpr int ST = TWW > 0 ? HaloGeom<(TWW > 0 ? TWW : 1)>::ST : kFlexST;
+  const int CP = C + 2;       // staged words per row (the pads included)
   constexpr int NSTG = 6;     // staged global words per thread
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-  const int X0 = tx * TWW * 32, Y0 = ty * p.th;
+  const int TW = TWW > 0 ? TWW : p.tww;
+  const int X0 = tx * TW * 32, Y0 = ty * p.th;
   const int XL = X0 - 32, YT = Y0 - 16;
-  const int xend = min(X0 + TWW * 32, p.L), yend = min(Y0 + p.th, p.L);
+  const int xend = min(X0 + TW * 32, p.L), yend = min(Y0 + p.th, p.L);
   const int total = p.R * CP;
   const uint64_t t = p.t0;
   // true (wrapped) row of every LDS row and true column of every LDS word
@@ -654,8 +678,8 @@ __device__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile)
     const int a = (int)(cls >> 1);
     // pairs start on even rows, so the active row of every pair is the class
     // parity: a uniform branch keeps each row's random state in registers
-    if (cls & 1u) count += halo_phase<TWW, KU, 1>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
-    else count += halo_phase<TWW, KU, 0>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
+    if (cls & 1u) count += halo_phase<ST, KU, 1>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
+    else count += halo_phase<ST, KU, 0>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
     __syncthreads();
   }
 
@@ -782,7 +806,7 @@ __device__ __forceinline__ unsigned cyc_phase(uint32_t* S, const SweepParams& p,
 // Whole lattice in one workgroup, p.nsweeps sweeps from p.t0.  Returns the
 // thread's accepted count.
 template <int LAYOUT, int C, int KU>
-__device__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
+__device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
   constexpr int ST = CycGeom<C>::ST;
   const int R = p.R;  // == L
   const int L = p.L;
@@ -793,7 +817,7 @@ __device__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
     int y = rr - 2, x = ww - 1;
     y = y < 0 ? y + R : (y >= R ? y - R : y);
     x = x < 0 ? x + C : (x >= C ? x - C : x);
-    S[rr * ST + ww] = load_word_at<LAYOUT>(p, y, 32 * x);
+    S[rr * ST + ww] = load_word_any<LAYOUT>(p, y, 32 * x);
   }
   int base0[KU], yrow[KU * 2], xw[KU], ur[KU], uw[KU];
   uint32_t okm[KU * 4];  // [0, 2KU): class-0 pattern per row; [2KU, 4KU): count mask per row
@@ -842,7 +866,7 @@ __device__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
   }
   for (int i = threadIdx.x; i < R * C; i += blockDim.x) {
     const int y = i / C, x = i - y * C;
-    store_word<LAYOUT>(p, y, 32 * x, S[(y + 2) * ST + x + 1], 32);
+    store_word_any<LAYOUT>(p, y, 32 * x, S[(y + 2) * ST + x + 1], 32);
   }
   return count;
 }
@@ -870,9 +894,9 @@ __global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepPa
     p.dst = bufs[2 * job.rep + ((s + 1u) & 1u)];
     p.t0 += s;
     unsigned count;
-    if (p.layout == kLayoutBits) count = halo_tile_sweep<kLayoutBits, kBatchTww, 2>(S, p, job.tile);
-    else count = halo_tile_sweep<kLayoutInt8, kBatchTww, 2>(S, p, job.tile);
-    add_block_count(S + p.R * HaloGeom<kBatchTww>::ST, count, p.accepted + job.tile);
+    if (p.layout == kLayoutBits) count = halo_tile_sweep<kLayoutBits, 0, 2>(S, p, job.tile);
+    else count = halo_tile_sweep<kLayoutInt8, 0, 2>(S, p, job.tile);
+    add_block_count(S + p.R * kFlexST, count, p.accepted + job.tile);
   }
   // the last workgroup to finish advances the sweep index for the next launch
   if (threadIdx.x == 0) {
@@ -886,25 +910,25 @@ __global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepPa
   }
 }
 
-template <int LAYOUT>
-__device__ unsigned resident_dispatch(uint32_t* S, const SweepParams& p) {
-  switch (p.C) {
-    case 2: return cyc_sweeps<LAYOUT, 2, 2>(S, p);
-    case 3: return cyc_sweeps<LAYOUT, 3, 2>(S, p);
-    case 4: return cyc_sweeps<LAYOUT, 4, 2>(S, p);
-    case 5: return cyc_sweeps<LAYOUT, 5, 2>(S, p);
-    case 6: return cyc_sweeps<LAYOUT, 6, 2>(S, p);
-    case 7: return cyc_sweeps<LAYOUT, 7, 2>(S, p);
-    default: return cyc_sweeps<LAYOUT, 8, 2>(S, p);
-  }
-}
-
-__global__ __launch_bounds__(kBatchThreads) void batch_resident_kernel(const SweepParams* reps, const int* ids) {
+// All resident replicas in one launch, one workgroup each: the width is a
+// uniform run-time switch over per-width instantiations (disjoint code regions
+// share one register allocation) and the layout is a run-time branch of the
+// staging and the final store.  The reduction area sits past the largest
+// resident lattice (rows L+4, stride <= 36).
+__global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const SweepParams* reps, const int* ids) {
   extern __shared__ uint32_t S[];
   const SweepParams p = reps[ids[blockIdx.x]];
-  const unsigned count = (p.layout == kLayoutBits) ? resident_dispatch<kLayoutBits>(S, p)
-                                                   : resident_dispatch<kLayoutInt8>(S, p);
-  // the reduction area sits past the largest resident tile (rows L+4, stride <= 36)
+  unsigned count;
+  switch (p.C) {
+    case 2: count = cyc_sweeps<0, 2, 2>(S, p); break;
+    case 3: count = cyc_sweeps<0, 3, 2>(S, p); break;
+    case 4: count = cyc_sweeps<0, 4, 2>(S, p); break;
+    case 5: count = cyc_sweeps<0, 5, 2>(S, p); break;
+    case 6: count = cyc_sweeps<0, 6, 2>(S, p); break;
+    case 7: count = cyc_sweeps<0, 7, 2>(S, p); break;
+    case 8: count = cyc_sweeps<0, 8, 2>(S, p); break;
+    default: count = cyc_sweeps<0, 9, 2>(S, p); break;
+  }
   add_block_count(S + (p.R + 4) * 36, count, p.accepted);
 }
 
@@ -977,7 +1001,7 @@ namespace kk {
 
 size_t batch_tile_lds_bytes() {
   const int R = kBatchTh + 32;
-  return ((size_t)R * HaloGeom<kBatchTww>::ST + 16 + R + HaloGeom<kBatchTww>::C) * sizeof(uint32_t);
+  return ((size_t)R * kFlexST + 16 + R + kBatchMaxTww + 2) * sizeof(uint32_t);
 }
 
 size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * sizeof(uint32_t); }
@@ -991,7 +1015,7 @@ hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const 
 
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
                                  hipStream_t stream) {
-  hipLaunchKernelGGL(batch_resident_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
+  hipLaunchKernelGGL(batch_resident_all_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
   return hipGetLastError();
 }
 
