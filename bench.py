@@ -10,7 +10,9 @@ histogram of species 1.  The line also carries:
   * cpu_baseline -- the CPU oracle timed on a bounded sample of the same
     workload on this host;
   * batched -- aggregate attempts/s of the batch engine against the same
-    replicas run one after another through the plain path (when available).
+    replicas run one after another through the plain path;
+  * serving -- p50/p99 latency, served and offered attempts/s of the job
+    server replaying the Poisson job trace, saturated and below saturation.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -105,6 +107,27 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int):
             "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
 
 
+def serving(n_saturated: int, n_light: int, light_rate: float, chunk: int):
+    """Replay the Poisson job trace through the job server: once at its own
+    arrival rate (200 jobs/s, far above what one GPU serves) and once at a rate
+    below saturation."""
+    from paper_1309_4349_amd import serve
+    from paper_1309_4349_amd import workloads as wl
+
+    out = {"workload": "Poisson arrivals, L uniform over {128,256,512,1024,2048}, sweeps log-uniform 1e3..1e5, "
+                       "x~U[0.2,0.8], omega~U[0.2,1.4]", "chunk_sweeps": chunk}
+    sat = wl.serving_trace(n_jobs=n_saturated, rate=200.0)
+    log(f"[bench] serving: {len(sat)} jobs at 200 jobs/s")
+    out["saturated"] = serve.run_trace(sat, chunk_sweeps=chunk, log=None)
+    log(f"[bench] serving saturated: {out['saturated']}")
+    if n_light:
+        light = wl.serving_trace(n_jobs=n_light, rate=light_rate, seed=wl.MASTER_SEED ^ 5)
+        log(f"[bench] serving: {len(light)} jobs at {light_rate} jobs/s")
+        out["below_saturation"] = serve.run_trace(light, chunk_sweeps=chunk, log=None)
+        log(f"[bench] serving below saturation: {out['below_saturation']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +139,11 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=10_000, help="sweeps per replica in the batch run")
     ap.add_argument("--batch-plain-sweeps", type=int, default=500,
                     help="sweeps per replica for the one-at-a-time plain baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the job-server trace replay")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the saturated serving trace")
+    ap.add_argument("--serve-light-jobs", type=int, default=60, help="jobs of the below-saturation trace")
+    ap.add_argument("--serve-light-rate", type=float, default=5.0, help="arrival rate of the below-saturation trace")
+    ap.add_argument("--serve-chunk", type=int, default=1000, help="sweeps per server step")
     ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
@@ -191,6 +219,10 @@ def main():
     if not args.no_batch:
         batched = batched_vs_plain(args.batch_sweeps, args.batch_plain_sweeps)
 
+    served = None
+    if not args.no_serve:
+        served = serving(args.serve_jobs, args.serve_light_jobs, args.serve_light_rate, args.serve_chunk)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
@@ -210,6 +242,8 @@ def main():
     }
     if batched is not None:
         line["batched"] = batched
+    if served is not None:
+        line["serving"] = served
     print(json.dumps(line), flush=True)
 
 

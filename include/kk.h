@@ -175,6 +175,95 @@ kk_status kk_batch_info(kk_batch *b, size_t *n_resident, size_t *n_tiled, size_t
 
 void kk_batch_destroy(kk_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Job server: independent simulation jobs (a kk_replica each, `sweeps` being
+ * the job's total) arrive at any time and are served on one device.
+ *
+ *  - Admission: jobs wait in arrival (FIFO) order until their device memory
+ *    fits hbm_budget_bytes next to the jobs already admitted and a slot of
+ *    max_active is free.  A job's charge is an upper bound of what it holds:
+ *    two lattice buffers plus 8 bytes per site (placement keys, later the
+ *    cluster labels) plus small tables.  A job that alone exceeds the budget
+ *    is refused at submission (KK_ENOMEM).
+ *  - Continuous batching: each kk_server_step advances every admitted job by
+ *    min(chunk_sweeps, sweeps left) sweeps in one batch run (the batch engine
+ *    above), retires the jobs that are done and admits waiting ones; jobs join
+ *    and leave only between steps.
+ *  - Results: for a finished job, N_AB and E/kT = omega * N_AB of the final
+ *    lattice, the accepted-move count and the cluster-size histogram of
+ *    species 1 (as kk_cluster_hist), plus the final lattice if keep_lattice
+ *    is set.  Each equals what kk_create_ex + kk_sweep(sweeps) gives for the
+ *    job alone, whatever else runs beside it.
+ *  - Times are seconds on the server's monotonic clock (kk_server_now; zero at
+ *    creation).  Latency = t_done - t_arrival.
+ * The server is driven by one host thread; calls on one server must not
+ * overlap.  Paper: the many short and long simulations its kinetic study
+ * needs (section "Results"), served together; this is the throughput side of
+ * the method, not a step of it.
+ * ------------------------------------------------------------------------- */
+typedef struct kk_server kk_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* device bytes admitted jobs may hold together; 0 = 3/4 of free memory */
+    uint32_t max_active;       /* jobs advanced together; 0 = 256 */
+    uint32_t keep_lattice;     /* nonzero: keep each finished lattice on the host */
+    uint64_t chunk_sweeps;     /* sweeps per step; 0 = 1000; below 2^31 */
+    void *hip_stream;          /* hipStream_t for uploads and joins; NULL = own */
+} kk_server_config;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;            /* KK_OK, or the error that ended the job */
+    uint32_t L;
+    uint64_t sweeps, attempts, accepted;
+    uint64_t n_unlike;         /* N_AB of the final lattice */
+    double energy_kT;          /* omega * N_AB */
+    double t_arrival, t_admit, t_done;
+    uint64_t hist_entries;     /* entries of the species-1 cluster histogram */
+} kk_job_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, steps;
+    uint64_t queued, active;
+    uint64_t bytes_in_use, peak_bytes, budget;
+    uint64_t attempts;         /* attempts made by all steps so far */
+    double gpu_busy_s;         /* wall time spent inside batch runs */
+} kk_server_stats;
+
+/* cfg may be NULL (all defaults). */
+kk_status kk_server_create(kk_server **out, const kk_server_config *cfg);
+
+/* Current time on the server clock. */
+kk_status kk_server_now(kk_server *s, double *t);
+
+/* Queue a job (validated as kk_create_ex would, plus the budget check).
+ * arrival_s < 0 stamps the arrival now; otherwise it is taken as given (a
+ * trace replayer passes the scheduled arrival).  *job_id receives the id. */
+kk_status kk_server_submit(kk_server *s, const kk_replica *job, double arrival_s, uint64_t *job_id);
+
+/* Admit, advance every admitted job by one chunk (blocking), retire finished
+ * jobs, admit again.  Returns the admitted and waiting counts. */
+kk_status kk_server_step(kk_server *s, size_t *n_active, size_t *n_queued);
+
+/* Move up to cap finished, not yet polled results into out (completion
+ * order); *n_out receives the number written (the rest stay for later). */
+kk_status kk_server_poll(kk_server *s, kk_job_result *out, size_t cap, size_t *n_out);
+
+/* A finished job's species-1 histogram (ascending size); KK_ETRUNC with
+ * *n_out = the entry count when cap is too small. */
+kk_status kk_server_job_hist(kk_server *s, uint64_t job_id, kk_hist_entry *out, size_t cap, size_t *n_out);
+
+/* A finished job's final lattice as L*L bytes of 0/1 (needs keep_lattice). */
+kk_status kk_server_job_lattice(kk_server *s, uint64_t job_id, uint8_t *out, size_t n);
+
+/* Drop a finished, polled job's host-side results. */
+kk_status kk_server_release(kk_server *s, uint64_t job_id);
+
+kk_status kk_server_get_stats(kk_server *s, kk_server_stats *out);
+
+/* Frees every job, queued, running or finished. */
+void kk_server_destroy(kk_server *s);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *kk_last_error(void);
 

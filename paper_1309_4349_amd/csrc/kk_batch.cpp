@@ -1,16 +1,20 @@
 // kk_batch.cpp -- many independent lattices (replicas) of uneven size,
 // composition and omega advanced together on one GPU.
 //
-// Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <= 288)
-// are "resident": one persistent launch gives each its own workgroup, which
-// keeps the lattice in LDS for all of its sweeps.  The others are "tiled":
-// they are split into a few groups of equal work; for each group every sweep
-// is one launch over all of the group's halo tiles, and those launches are
-// captured in a HIP graph that is replayed.  The resident launch and the
-// groups run concurrently, each on its own stream (few streams in all: the
-// device multiplexes streams over a small number of hardware queues, and two
-// streams sharing one queue serialise).  No slot or replica index enters any random
-// counter, so every replica ends exactly where kk_sweep would have left it.
+// Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <=
+// 32 * kResidentMaxC) are "resident": one persistent launch gives each its own
+// workgroup, which keeps the lattice in LDS for all of its sweeps.  The others
+// are "tiled": they are split into a few groups of equal work; for each group
+// every sweep is one launch over all of the group's halo tiles, and those
+// launches are captured in a HIP graph that is replayed.  The resident launch
+// and the groups run concurrently, each on its own stream (few streams in
+// all: the device multiplexes streams over a small number of hardware queues,
+// and two streams sharing one queue serialise).  No slot or replica index
+// enters any random counter, so every replica ends exactly where kk_sweep
+// would have left it.
+//
+// The streams live as long as the batch; the plan (tables, graphs) is rebuilt
+// whenever the replica set changes, which the job server does between steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,34 +27,38 @@
 
 using namespace kk;
 
+namespace {
+constexpr int kMaxTileGroups = 4;
+}
+
 struct kk_batch {
   std::vector<kk_sim*> sims;
   std::vector<uint64_t> sweeps;
+  bool own_sims = true;
+  // streams and events, created once
+  hipStream_t sA = nullptr, sB = nullptr;  // resident launch; uploads and joins
+  bool own_sB = false;
+  hipEvent_t ev_upload = nullptr, ev_res = nullptr;
+  hipStream_t tg_stream[kMaxTileGroups] = {};
+  hipEvent_t tg_done[kMaxTileGroups] = {};
+  // plan, rebuilt by batch_plan
   std::vector<int> resident, tiled;
   std::vector<size_t> count_off, count_n;
   size_t ncounts = 0;
-  hipStream_t sA = nullptr, sB = nullptr;
-  bool own_sB = false;
-  hipEvent_t ev_upload = nullptr, ev_done = nullptr, ev_res = nullptr;
+  std::vector<int> tg_off, tg_n;  // tiled groups: slices of the tile-job table
+  std::vector<int> job_rep;       // host copy: replica of every tile job
+  std::vector<hipGraph_t> tg_graph;
+  std::vector<hipGraphExec_t> tg_exec;
+  std::vector<int> tg_k;          // sweep launches per replay of each group's graph
   SweepParams* d_params = nullptr;
   void** d_bufs = nullptr;
   unsigned long long* d_nsw = nullptr;
   BatchTileJob* d_jobs = nullptr;
   int njobs = 0;
-  // tiled replicas split into work-balanced groups, each with its own stream,
-  // sweep counter and captured graph, so that the groups' launches overlap
-  std::vector<int> tg_off, tg_n;
-  std::vector<int> job_rep;  // host copy: replica of every tile job
-  std::vector<uint64_t> tg_maxsw;
-  std::vector<hipStream_t> tg_stream;
-  std::vector<hipGraph_t> tg_graph;
-  std::vector<hipGraphExec_t> tg_exec;
-  std::vector<hipEvent_t> tg_done;
   int* d_res = nullptr;
   size_t res_lds = 0;
   unsigned* d_ctl = nullptr;
   unsigned long long* d_counts = nullptr;
-  int graph_k = 0;
   bool poisoned = false;
 };
 
@@ -66,24 +74,70 @@ namespace {
     }                                                                                             \
   } while (0)
 
-int jobs_rep(const kk_batch* b, int q) { return b->job_rep[q]; }
-
 bool is_resident(const kk_sim* h) { return h->L % 32 == 0 && h->L >= 64 && h->L / 32 <= kResidentMaxC; }
 
-void free_batch(kk_batch* b) {
-  for (hipGraphExec_t ge : b->tg_exec) (void)hipGraphExecDestroy(ge);
-  for (hipGraph_t g : b->tg_graph) (void)hipGraphDestroy(g);
-  for (hipStream_t st : b->tg_stream) (void)hipStreamDestroy(st);
-  for (hipEvent_t ev : b->tg_done) (void)hipEventDestroy(ev);
+void clear_plan(kk_batch* b) {
+  for (hipGraphExec_t ge : b->tg_exec)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  for (hipGraph_t g : b->tg_graph)
+    if (g) (void)hipGraphDestroy(g);
+  b->tg_exec.clear();
+  b->tg_graph.clear();
+  b->tg_k.clear();
   for (void* p : {(void*)b->d_params, (void*)b->d_bufs, (void*)b->d_nsw, (void*)b->d_jobs, (void*)b->d_res,
                   (void*)b->d_ctl, (void*)b->d_counts})
     if (p) (void)hipFree(p);
-  for (kk_sim* h : b->sims) kk_destroy(h);
-  if (b->ev_res) (void)hipEventDestroy(b->ev_res);
+  b->d_params = nullptr;
+  b->d_bufs = nullptr;
+  b->d_nsw = nullptr;
+  b->d_jobs = nullptr;
+  b->d_res = nullptr;
+  b->d_ctl = nullptr;
+  b->d_counts = nullptr;
+  b->resident.clear();
+  b->tiled.clear();
+  b->count_off.clear();
+  b->count_n.clear();
+  b->ncounts = 0;
+  b->tg_off.clear();
+  b->tg_n.clear();
+  b->job_rep.clear();
+  b->njobs = 0;
+  b->res_lds = 0;
+}
+
+void free_batch(kk_batch* b) {
+  clear_plan(b);
+  if (b->own_sims)
+    for (kk_sim* h : b->sims) kk_destroy(h);
+  b->sims.clear();
+  for (int g = 0; g < kMaxTileGroups; ++g) {
+    if (b->tg_stream[g]) (void)hipStreamDestroy(b->tg_stream[g]);
+    if (b->tg_done[g]) (void)hipEventDestroy(b->tg_done[g]);
+  }
   if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
-  if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  if (b->ev_res) (void)hipEventDestroy(b->ev_res);
   if (b->sA) (void)hipStreamDestroy(b->sA);
   if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
+}
+
+kk_status make_streams(kk_batch* b, void* hip_stream) {
+  hipError_t e;
+  if (hip_stream) b->sB = static_cast<hipStream_t>(hip_stream);
+  else {
+    if ((e = hipStreamCreateWithFlags(&b->sB, hipStreamNonBlocking)) != hipSuccess)
+      return set_error(KK_EDEVICE, "stream: %s", hipGetErrorString(e));
+    b->own_sB = true;
+  }
+  if ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess)
+    return set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e));
+  for (int g = 0; g < kMaxTileGroups; ++g)
+    if ((e = hipStreamCreateWithFlags(&b->tg_stream[g], hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->tg_done[g], hipEventDisableTiming)) != hipSuccess)
+      return set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e));
+  return KK_OK;
 }
 
 // Geometry of a replica's batch launch (resident: whole lattice; tiled: fixed tile).
@@ -111,40 +165,14 @@ void batch_geometry(const kk_sim* h, bool resident, SweepParams* p) {
   p->layout = h->layout;
 }
 
-}  // namespace
+int graph_launches(uint64_t max_sweeps) { return (int)std::max<uint64_t>(1, std::min<uint64_t>(max_sweeps, 64)); }
 
-extern "C" {
-
-kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void* hip_stream) {
-  if (!out) return set_error(KK_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!reps || n == 0) return set_error(KK_EINVAL, "need at least one replica");
-  kk_batch* b = new (std::nothrow) kk_batch();
-  if (!b) return set_error(KK_ENOMEM, "host allocation failed");
-  auto fail = [&](kk_status st) {
-    free_batch(b);
-    delete b;
-    return st;
-  };
-  hipError_t e;
-  if (hip_stream) b->sB = static_cast<hipStream_t>(hip_stream);
-  else {
-    if ((e = hipStreamCreateWithFlags(&b->sB, hipStreamNonBlocking)) != hipSuccess)
-      return fail(set_error(KK_EDEVICE, "stream: %s", hipGetErrorString(e)));
-    b->own_sB = true;
-  }
-  if ((e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming)) != hipSuccess)
-    return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
-  for (size_t i = 0; i < n; ++i) {
-    kk_sim* h = nullptr;
-    kk_status st = kk_create_ex(&h, reps[i].L, reps[i].composition, reps[i].omega_kT, reps[i].seed, reps[i].layout,
-                                b->sB);
-    if (st != KK_OK) return fail(st);
-    b->sims.push_back(h);
-    b->sweeps.push_back(reps[i].sweeps);
-  }
-  // plan: resident replicas and the tile jobs of the others
+// Plan the current replica set: resident list, tile jobs split into groups of
+// equal work, device tables and one captured graph per group.
+kk_status batch_plan(kk_batch* b) {
+  clear_plan(b);
+  const size_t n = b->sims.size();
+  if (n == 0) return KK_OK;
   std::vector<BatchTileJob> jobs;
   for (size_t i = 0; i < n; ++i) {
     kk_sim* h = b->sims[i];
@@ -162,13 +190,14 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
       b->tiled.push_back((int)i);
     }
   }
-  // LPT split of the tiled replicas into groups by work per sweep
-  const int ngroups = (int)std::min<size_t>(b->resident.empty() ? 4 : 3, b->tiled.size());
+  // longest-processing-time split of the tiled replicas by work per run
+  const int ngroups = (int)std::min<size_t>(b->resident.empty() ? kMaxTileGroups : kMaxTileGroups - 1,
+                                            b->tiled.size());
   std::vector<std::vector<int>> groups(ngroups);
   {
     std::vector<int> order = b->tiled;
     auto work = [&](int i) { return (double)b->sims[i]->L * b->sims[i]->L * (double)b->sweeps[i]; };
-    std::sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
     std::vector<double> load(ngroups, 0.0);
     for (int i : order) {
       const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -176,69 +205,123 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
       load[g] += work(i);
     }
   }
+  std::vector<uint64_t> maxsw(ngroups, 0);
   for (int g = 0; g < ngroups; ++g) {
     b->tg_off.push_back((int)jobs.size());
-    uint64_t mx = 0;
     for (int i : groups[g]) {
       for (size_t t = 0; t < b->count_n[i]; ++t) jobs.push_back(BatchTileJob{i, (int)t});
-      mx = std::max(mx, b->sweeps[i]);
+      maxsw[g] = std::max(maxsw[g], b->sweeps[i]);
     }
     b->tg_n.push_back((int)jobs.size() - b->tg_off.back());
-    b->tg_maxsw.push_back(mx);
   }
   b->njobs = (int)jobs.size();
   for (const BatchTileJob& j : jobs) b->job_rep.push_back(j.rep);
   // resident replicas: one launch, widest lattices first (they run longest)
   std::stable_sort(b->resident.begin(), b->resident.end(),
                    [&](int a, int c) { return b->sims[a]->L > b->sims[c]->L; });
-  if (!b->resident.empty() &&
-      ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
-       (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess))
-    return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
   kk_status st = KK_OK;
   if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
   if (st == KK_OK) st = device_alloc((void**)&b->d_bufs, 2 * n * sizeof(void*));
   if (st == KK_OK) st = device_alloc((void**)&b->d_nsw, n * sizeof(unsigned long long));
-  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * std::max<size_t>(1, b->tg_n.size()));
+  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * kMaxTileGroups);
   if (st == KK_OK) st = device_alloc((void**)&b->d_counts, b->ncounts * sizeof(unsigned long long));
   if (st == KK_OK && b->njobs) st = device_alloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchTileJob));
   if (st == KK_OK && !b->resident.empty()) st = device_alloc((void**)&b->d_res, b->resident.size() * sizeof(int));
-  if (st != KK_OK) return fail(st);
+  if (st != KK_OK) return st;
+  hipError_t e;
   if (b->njobs && (e = hipMemcpy(b->d_jobs, jobs.data(), jobs.size() * sizeof(BatchTileJob),
                                  hipMemcpyHostToDevice)) != hipSuccess)
-    return fail(set_error(KK_EDEVICE, "upload jobs: %s", hipGetErrorString(e)));
+    return set_error(KK_EDEVICE, "upload jobs: %s", hipGetErrorString(e));
   if (!b->resident.empty() && (e = hipMemcpy(b->d_res, b->resident.data(), b->resident.size() * sizeof(int),
                                              hipMemcpyHostToDevice)) != hipSuccess)
-    return fail(set_error(KK_EDEVICE, "upload ids: %s", hipGetErrorString(e)));
-  // per group: a captured graph of graph_k sweep launches over the group's tile jobs
-  for (size_t g = 0; g < b->tg_n.size(); ++g) {
-    hipStream_t st = nullptr;
-    hipEvent_t ev = nullptr;
-    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-      return fail(set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e)));
-    b->tg_stream.push_back(st);
-    b->tg_done.push_back(ev);
-    if (b->tg_n[g] == 0) {
-      b->tg_graph.push_back(nullptr);
-      b->tg_exec.push_back(nullptr);
-      continue;
-    }
-    const int k = (int)std::max<uint64_t>(1, std::min<uint64_t>(b->tg_maxsw[g], 64));
-    b->graph_k = std::max(b->graph_k, k);
+    return set_error(KK_EDEVICE, "upload ids: %s", hipGetErrorString(e));
+  // per group: a captured graph of k sweep launches over the group's tile jobs
+  for (int g = 0; g < ngroups; ++g) {
+    hipStream_t s = b->tg_stream[g];
+    const int k = graph_launches(maxsw[g]);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return fail(set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e)));
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e));
     for (int r = 0; r < k; ++r)
       (void)launch_batch_tiles(b->d_params, b->d_bufs, b->d_nsw, b->d_jobs + b->tg_off[g], b->tg_n[g],
-                               b->d_ctl + 2 * g, st);
-    e = hipStreamEndCapture(st, &graph);
+                               b->d_ctl + 2 * g, s);
+    e = hipStreamEndCapture(s, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     b->tg_graph.push_back(graph);
     b->tg_exec.push_back(exec);
-    if (e != hipSuccess) return fail(set_error(KK_EDEVICE, "graph: %s", hipGetErrorString(e)));
+    b->tg_k.push_back(k);
+    if (e != hipSuccess) return set_error(KK_EDEVICE, "graph: %s", hipGetErrorString(e));
   }
+  return KK_OK;
+}
+
+}  // namespace
+
+namespace kk {
+
+kk_status batch_replan(kk_batch* b, const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps) {
+  if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  if (sims.size() != sweeps.size()) return set_error(KK_EINVAL, "sims and sweeps differ in length");
+  b->sims = sims;
+  b->sweeps = sweeps;
+  const kk_status st = batch_plan(b);
+  if (st != KK_OK) b->poisoned = true;
+  return st;
+}
+
+kk_status batch_over(const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps, void* hip_stream,
+                     kk_batch** out) {
+  *out = nullptr;
+  kk_batch* b = new (std::nothrow) kk_batch();
+  if (!b) return set_error(KK_ENOMEM, "host allocation failed");
+  b->own_sims = false;
+  kk_status st = make_streams(b, hip_stream);
+  if (st == KK_OK) st = batch_replan(b, sims, sweeps);
+  if (st != KK_OK) {
+    free_batch(b);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return KK_OK;
+}
+
+kk_status batch_set_sweeps(kk_batch* b, const std::vector<uint64_t>& sweeps) {
+  if (sweeps.size() != b->sims.size()) return set_error(KK_EINVAL, "sweeps differ in length");
+  b->sweeps = sweeps;
+  return KK_OK;
+}
+
+}  // namespace kk
+
+extern "C" {
+
+kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void* hip_stream) {
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!reps || n == 0) return set_error(KK_EINVAL, "need at least one replica");
+  kk_batch* b = new (std::nothrow) kk_batch();
+  if (!b) return set_error(KK_ENOMEM, "host allocation failed");
+  auto fail = [&](kk_status st) {
+    free_batch(b);
+    delete b;
+    return st;
+  };
+  kk_status st = make_streams(b, hip_stream);
+  if (st != KK_OK) return fail(st);
+  std::vector<kk_sim*> sims;
+  std::vector<uint64_t> sweeps;
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = nullptr;
+    st = kk_create_ex(&h, reps[i].L, reps[i].composition, reps[i].omega_kT, reps[i].seed, reps[i].layout, b->sB);
+    if (st != KK_OK) return fail(st);
+    b->sims.push_back(h);  // owned from here on, also if planning fails
+    sims.push_back(h);
+    sweeps.push_back(reps[i].sweeps);
+  }
+  st = batch_replan(b, sims, sweeps);
+  if (st != KK_OK) return fail(st);
   *out = b;
   return KK_OK;
 }
@@ -247,6 +330,7 @@ kk_status kk_batch_run(kk_batch* b) {
   if (!b) return set_error(KK_EINVAL, "NULL batch");
   if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
   const size_t n = b->sims.size();
+  if (n == 0) return KK_OK;
   std::vector<SweepParams> params(n);
   std::vector<void*> bufs(2 * n);
   std::vector<unsigned long long> nsw(n);
@@ -255,6 +339,7 @@ kk_status kk_batch_run(kk_batch* b) {
     if (h->poisoned) return set_error(KK_ESTATE, "replica %zu poisoned", i);
     if (h->t + b->sweeps[i] >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "sweep counter overflow");
     const bool res = is_resident(h);
+    if (res && b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per run");
     SweepParams& p = params[i];
     batch_geometry(h, res, &p);
     p.t0 = h->t;
@@ -262,35 +347,34 @@ kk_status kk_batch_run(kk_batch* b) {
     bufs[2 * i] = h->lat[h->cur];
     bufs[2 * i + 1] = h->lat[h->cur ^ 1];
     p.src = p.dst = h->lat[h->cur];
-    p.nsweeps = (int)b->sweeps[i];
+    p.nsweeps = (int)std::min<uint64_t>(b->sweeps[i], 0x7FFFFFFFull);
     nsw[i] = b->sweeps[i];
   }
-  for (int i : b->resident)
-    if (b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per run");
+  // every replica's own stream has finished its earlier work (placement, queries)
+  for (kk_sim* h : b->sims)
+    if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
   KB_HIP(hipMemcpyAsync(b->d_params, params.data(), n * sizeof(SweepParams), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemcpyAsync(b->d_bufs, bufs.data(), 2 * n * sizeof(void*), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemcpyAsync(b->d_nsw, nsw.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
-  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * std::max<size_t>(1, b->tg_n.size()), b->sB));
+  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * kMaxTileGroups, b->sB));
   KB_HIP(hipEventRecord(b->ev_upload, b->sB));
   if (!b->resident.empty()) {
     KB_HIP(hipStreamWaitEvent(b->sA, b->ev_upload, 0));
     KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->resident.size(), b->res_lds, b->sA));
     KB_HIP(hipEventRecord(b->ev_res, b->sA));
   }
-  for (size_t g = 0; g < b->tg_n.size(); ++g) {
-    if (!b->tg_exec[g]) continue;
-    hipStream_t st = b->tg_stream[g];
-    KB_HIP(hipStreamWaitEvent(st, b->ev_upload, 0));
+  for (size_t g = 0; g < b->tg_exec.size(); ++g) {
+    hipStream_t s = b->tg_stream[g];
+    KB_HIP(hipStreamWaitEvent(s, b->ev_upload, 0));
     uint64_t mx = 0;
-    for (int q = b->tg_off[g]; q < b->tg_off[g] + b->tg_n[g]; ++q) mx = std::max<uint64_t>(mx, nsw[jobs_rep(b, q)]);
-    const int k = (int)std::max<uint64_t>(1, std::min<uint64_t>(b->tg_maxsw[g], 64));
-    const uint64_t reps = (mx + k - 1) / k;
-    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->tg_exec[g], st));
-    KB_HIP(hipEventRecord(b->tg_done[g], st));
+    for (int q = b->tg_off[g]; q < b->tg_off[g] + b->tg_n[g]; ++q) mx = std::max<uint64_t>(mx, nsw[b->job_rep[q]]);
+    const uint64_t reps = (mx + b->tg_k[g] - 1) / b->tg_k[g];
+    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->tg_exec[g], s));
+    KB_HIP(hipEventRecord(b->tg_done[g], s));
   }
   if (!b->resident.empty()) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
-  for (hipEvent_t ev : b->tg_done) KB_HIP(hipStreamWaitEvent(b->sB, ev, 0));
+  for (size_t g = 0; g < b->tg_exec.size(); ++g) KB_HIP(hipStreamWaitEvent(b->sB, b->tg_done[g], 0));
   KB_HIP(hipStreamSynchronize(b->sB));
   std::vector<unsigned long long> counts(b->ncounts);
   KB_HIP(hipMemcpy(counts.data(), b->d_counts, b->ncounts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -323,6 +407,8 @@ void kk_batch_destroy(kk_batch* b) {
   if (!b) return;
   if (b->sB) (void)hipStreamSynchronize(b->sB);
   if (b->sA) (void)hipStreamSynchronize(b->sA);
+  for (int g = 0; g < kMaxTileGroups; ++g)
+    if (b->tg_stream[g]) (void)hipStreamSynchronize(b->tg_stream[g]);
   free_batch(b);
   delete b;
 }

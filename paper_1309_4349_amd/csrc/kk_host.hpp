@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/kk.h"
 #include "kk_kernels.hpp"
@@ -58,4 +59,11 @@ namespace kk {
 // helpers shared with the batch engine (kk_api.cpp)
 kk_status device_alloc(void** p, size_t bytes);
 kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t n);
+
+// batch engine over borrowed handles (kk_batch.cpp), used by the job server:
+// the batch never destroys these sims; replan after the set changes.
+kk_status batch_over(const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps, void* hip_stream,
+                     kk_batch** out);
+kk_status batch_replan(kk_batch* b, const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps);
+kk_status batch_set_sweeps(kk_batch* b, const std::vector<uint64_t>& sweeps);
 }  // namespace kk

@@ -24,6 +24,9 @@ EXPORTS = [
     "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_destroy",
+    "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
+    "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
+    "kk_server_destroy",
 ]
 
 
@@ -40,6 +43,32 @@ class HistEntry(ctypes.Structure):
 class Replica(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("composition", ctypes.c_double),
                 ("omega_kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("keep_lattice", ctypes.c_uint32), ("chunk_sweeps", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("L", ctypes.c_uint32),
+                ("sweeps", ctypes.c_uint64), ("attempts", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
+                ("n_unlike", ctypes.c_uint64), ("energy_kT", ctypes.c_double),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("hist_entries", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "steps", "queued", "active",
+                                               "bytes_in_use", "peak_bytes", "budget", "attempts")] + \
+               [("gpu_busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -81,6 +110,15 @@ def load(path: str = LIB_PATH):
         "kk_batch_run": [P],
         "kk_batch_sim": [P, ctypes.c_size_t, PP],
         "kk_batch_info": [P, szp, szp, szp],
+        "kk_server_create": [PP, ctypes.POINTER(ServerConfig)],
+        "kk_server_now": [P, dp],
+        "kk_server_submit": [P, ctypes.POINTER(Replica), D, u64p],
+        "kk_server_step": [P, szp, szp],
+        "kk_server_poll": [P, ctypes.POINTER(JobResult), ctypes.c_size_t, szp],
+        "kk_server_job_hist": [P, U64, ctypes.POINTER(HistEntry), ctypes.c_size_t, szp],
+        "kk_server_job_lattice": [P, U64, P, ctypes.c_size_t],
+        "kk_server_release": [P, U64],
+        "kk_server_get_stats": [P, ctypes.POINTER(ServerStats)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -90,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.kk_destroy.restype = None
     lib.kk_batch_destroy.argtypes = [P]
     lib.kk_batch_destroy.restype = None
+    lib.kk_server_destroy.argtypes = [P]
+    lib.kk_server_destroy.restype = None
     lib.kk_last_error.argtypes = []
     lib.kk_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -249,6 +289,86 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load().kk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _replica(j) -> Replica:
+    return Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
+                   j.seed & (2**64 - 1), int(j.sweeps))
+
+
+class Server:
+    """Job server (kk_server_*): FIFO admission under an HBM budget and
+    continuous batching in chunks of sweeps."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 0, chunk_sweeps: int = 0,
+                 keep_lattice: bool = False, stream: Optional[int] = None):
+        lib = load()
+        cfg = ServerConfig(hbm_budget_bytes, max_active, 1 if keep_lattice else 0, chunk_sweeps,
+                           ctypes.c_void_p(stream) if stream else None)
+        h = ctypes.c_void_p()
+        _check(lib.kk_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self._h = h
+        self.keep_lattice = keep_lattice
+        self.L = {}
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _check(load().kk_server_now(self._h, ctypes.byref(t)))
+        return t.value
+
+    def submit(self, job, arrival: float = -1.0) -> int:
+        r = _replica(job)
+        jid = ctypes.c_uint64()
+        _check(load().kk_server_submit(self._h, ctypes.byref(r), float(arrival), ctypes.byref(jid)))
+        self.L[jid.value] = job.L
+        return jid.value
+
+    def step(self) -> Tuple[int, int]:
+        a, q = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().kk_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, cap: int = 256) -> List[dict]:
+        buf = (JobResult * cap)()
+        n = ctypes.c_size_t()
+        _check(load().kk_server_poll(self._h, buf, cap, ctypes.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def job_hist(self, job_id: int) -> List[Tuple[int, int]]:
+        lib = load()
+        need = ctypes.c_size_t()
+        st = lib.kk_server_job_hist(self._h, job_id, None, 0, ctypes.byref(need))
+        if st not in (KK_OK, KK_ETRUNC):
+            _check(st)
+        buf = (HistEntry * max(1, need.value))()
+        _check(lib.kk_server_job_hist(self._h, job_id, buf, need.value, ctypes.byref(need)))
+        return [(int(buf[i].size), int(buf[i].count)) for i in range(need.value)]
+
+    def job_lattice(self, job_id: int) -> np.ndarray:
+        L = self.L[job_id]
+        out = np.empty((L, L), dtype=np.uint8)
+        _check(load().kk_server_job_lattice(self._h, job_id, out.ctypes.data, out.size))
+        return out
+
+    def release(self, job_id: int):
+        _check(load().kk_server_release(self._h, job_id))
+        self.L.pop(job_id, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().kk_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().kk_server_destroy(self._h)
             self._h = None
 
     def __del__(self):
