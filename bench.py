@@ -32,11 +32,18 @@ HBM_PEAK_GBS = 8000.0
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 VALU_PEAK_GOPS = CUS * LANES * CLOCK_HZ / 1e9   # int32 lane-ops/s, one VALU op per lane per clock
 
-# Algorithmic cost of one attempt of the bit-sliced sweep (derivation in the design notes):
-#   random planes: 3 Philox4x32-10 blocks per 32 sites per sweep, 40 VALU ops per block
-#   (10 rounds x [2 v_mad_u64_u32 + 2 v_xor3]) -> 120/32 = 3.75 ops per attempt;
-#   decision of 8 centres per 32-site word per phase: 116 ops -> 14.5 ops per attempt.
-OPS_PER_ATTEMPT = 3.75 + 14.5
+# Algorithmic cost of one attempt of the bit-sliced sweep, in 32-bit VALU lane-ops
+# (one lane-op = one 32-bit integer/bitwise operation on one lane):
+#   random planes: 3 Philox4x32-10 blocks per 32-site word per sweep, 10 rounds x
+#     (2 v_mad_u64_u32 + 2 three-input xors) = 40 per block -> 120 / 32      = 3.75
+#   threshold planes: 3 bit-sliced 10-bit compares (less-than and equal) per
+#     32-site word per sweep, 2 ops per bit -> 60 / 32                       = 1.875
+#   decision of the 8 centres of a word in one phase: 8 funnel shifts, 12
+#     partner/neighbour selects, 1 activity mask, 5 + 6 counter ops, 2 + 6 + 2
+#     threshold selection, 1 class-mask rotate = 43; applying the accepted
+#     swaps (4 direction splits, 3 + 3 shifts/xors) and counting them (2) = 13
+#     -> 56 / 8                                                              = 7.0
+OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
 BYTES_PER_ATTEMPT_BITS = 0.25   # read + write one bit per site per sweep
 BYTES_PER_ATTEMPT_INT8 = 2.0
 
@@ -206,7 +213,7 @@ def main():
     tw, th, ku = sim.get_tile()
     roofline = {"bound": "alu", "achieved": round(ops, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
                 "frac": round(ops / VALU_PEAK_GOPS, 4), "traffic": None,
-                "kernel": "sweep_kernel<bitpacked, halo tiles>",
+                "kernel": f"halo_kernel<bitpacked, {tw}, {ku}>",
                 "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
                 "ops_per_attempt": OPS_PER_ATTEMPT,
                 "hbm_achieved_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS,

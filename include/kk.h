@@ -133,9 +133,11 @@ kk_status kk_get_tile(kk_sim *h, uint32_t *tile_words, uint32_t *tile_rows, uint
  * their own work against it. */
 kk_status kk_stream(kk_sim *h, void **stream_out);
 
-/* Run n_sweeps sweeps recording a HIP event pair around every sweep-kernel
- * launch; *kernel_ms receives the summed kernel time and *launches the number
- * of sweep-kernel launches.  For profiling; results equal kk_sweep's. */
+/* Run n_sweeps sweeps with one HIP event pair on the handle's stream around
+ * all of their sweep-kernel launches, which run back to back; *kernel_ms
+ * receives the elapsed time between the events (kernel time plus any gaps
+ * between launches) and *launches the number of launches.  Blocking.  For
+ * profiling; results equal kk_sweep's. */
 kk_status kk_sweep_timed(kk_sim *h, uint64_t n_sweeps, double *kernel_ms, uint64_t *launches);
 
 void kk_destroy(kk_sim *h);

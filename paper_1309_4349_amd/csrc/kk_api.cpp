@@ -327,21 +327,15 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
     *kernel_ms = 0.0;
   }
   uint64_t nl = 0;
+  if (n > 0) h->epoch += 1;
+  if (kernel_ms) KK_HIP(hipEventRecord(ev[0], h->stream));
   while (n > 0) {
     const uint64_t k = n < per_launch ? n : per_launch;
     p.src = h->lat[h->cur];
     p.dst = h->lat[h->cur ^ 1];
     p.t0 = h->t;
     p.nsweeps = (int)k;
-    if (kernel_ms) KK_HIP(hipEventRecord(ev[0], h->stream));
     KK_HIP(launch_sweep(p, h->layout, h->tile.cyclic, h->tile.ku, threads, h->stream));
-    if (kernel_ms) {
-      KK_HIP(hipEventRecord(ev[1], h->stream));
-      KK_HIP(hipEventSynchronize(ev[1]));
-      float ms = 0.f;
-      KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-      *kernel_ms += ms;
-    }
     h->cur ^= 1;
     h->t += k;
     h->attempts += k * (uint64_t)h->L * (uint64_t)h->L;
@@ -349,6 +343,13 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
     ++nl;
   }
   if (kernel_ms) {
+    // one event pair around the back-to-back launches: the elapsed time is
+    // their summed duration plus whatever gaps the device leaves between them
+    KK_HIP(hipEventRecord(ev[1], h->stream));
+    KK_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *kernel_ms = ms;
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
   }
@@ -507,32 +508,37 @@ kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap
     if (st != KK_OK) return st;
     h->ccl_ready = true;
   }
-  KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
-  KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
-  KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
-  KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->stream));
-  std::vector<unsigned> hs(kSmallSizes);
-  unsigned nbig = 0;
-  KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
-  KK_HIP(hipMemcpyAsync(&nbig, h->ccl.big_count, 4, hipMemcpyDeviceToHost, h->stream));
-  KK_HIP(hipStreamSynchronize(h->stream));
-  if (nbig > h->ccl.big_cap) return set_error(KK_EDEVICE, "cluster list overflow (%u > %u)", nbig, h->ccl.big_cap);
-  std::vector<uint32_t> big(nbig);
-  if (nbig) {
-    KK_HIP(hipMemcpyAsync(big.data(), h->ccl.big, nbig * 4, hipMemcpyDeviceToHost, h->stream));
+  if (h->hist_epoch != h->epoch || h->hist_species != species) {
+    // label, count and histogram on the device; the result is cached until the
+    // lattice changes, so a size query followed by the fill labels only once
+    KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
+    KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
+    KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
+    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->stream));
+    std::vector<unsigned> hs(kSmallSizes);
+    unsigned nbig = 0;
+    KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
+    KK_HIP(hipMemcpyAsync(&nbig, h->ccl.big_count, 4, hipMemcpyDeviceToHost, h->stream));
     KK_HIP(hipStreamSynchronize(h->stream));
+    if (nbig > h->ccl.big_cap) return set_error(KK_EDEVICE, "cluster list overflow (%u > %u)", nbig, h->ccl.big_cap);
+    std::vector<uint32_t> big(nbig);
+    if (nbig) {
+      KK_HIP(hipMemcpyAsync(big.data(), h->ccl.big, nbig * 4, hipMemcpyDeviceToHost, h->stream));
+      KK_HIP(hipStreamSynchronize(h->stream));
+    }
+    std::map<uint64_t, uint64_t> bigh;
+    for (uint32_t s : big) bigh[s] += 1;
+    h->hist_cache.clear();
+    for (int s = 1; s < kSmallSizes; ++s)
+      if (hs[s]) h->hist_cache.push_back(kk_hist_entry{(uint64_t)s, (uint64_t)hs[s]});
+    for (auto& kv : bigh) h->hist_cache.push_back(kk_hist_entry{kv.first, kv.second});
+    h->hist_epoch = h->epoch;
+    h->hist_species = species;
   }
-  std::map<uint64_t, uint64_t> bigh;
-  for (uint32_t s : big) bigh[s] += 1;
-  size_t n = 0;
-  for (int s = 1; s < kSmallSizes; ++s) n += hs[s] != 0;
-  n += bigh.size();
+  const size_t n = h->hist_cache.size();
   *n_out = n;
   if (cap < n) return set_error(KK_ETRUNC, "histogram has %zu entries, cap %zu", n, cap);
-  size_t i = 0;
-  for (int s = 1; s < kSmallSizes; ++s)
-    if (hs[s]) out[i++] = kk_hist_entry{(uint64_t)s, (uint64_t)hs[s]};
-  for (auto& kv : bigh) out[i++] = kk_hist_entry{kv.first, kv.second};
+  std::copy(h->hist_cache.begin(), h->hist_cache.end(), out);
   return KK_OK;
 }
 
@@ -583,6 +589,7 @@ kk_status kk_set_lattice(kk_sim* h, const uint8_t* host_in, size_t n, uint64_t s
   }
   KK_HIP(hipStreamSynchronize(h->stream));
   h->t = sweep_t;
+  h->epoch += 1;
   return KK_OK;
 }
 

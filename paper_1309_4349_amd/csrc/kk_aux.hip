@@ -129,19 +129,24 @@ __device__ __forceinline__ uint32_t ld_parent(const uint32_t* parent, uint32_t x
   return __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t find_root(const uint32_t* parent, uint32_t x) {
+// Root of x with path halving: every visited node is re-linked to its
+// grandparent.  Links only ever decrease (atomicMin) and always point to an
+// ancestor in the same tree, so concurrent finds and unions stay consistent.
+__device__ __forceinline__ uint32_t find_root_halving(uint32_t* parent, uint32_t x) {
   uint32_t p = ld_parent(parent, x);
   while (p != x) {
+    const uint32_t g = ld_parent(parent, p);
+    if (g != p) atomicMin(&parent[x], g);
     x = p;
-    p = ld_parent(parent, x);
+    p = g;
   }
   return x;
 }
 
 __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
   for (;;) {
-    a = find_root(parent, a);
-    b = find_root(parent, b);
+    a = find_root_halving(parent, a);
+    b = find_root_halving(parent, b);
     if (a == b) return;
     if (a > b) {
       const uint32_t t = a;
@@ -174,12 +179,37 @@ __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, in
   }
 }
 
-__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, uint32_t* size) {
+// After all unions: point every site straight at its root.
+__global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L) {
   const size_t n = (size_t)L * L;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    if (parent[i] == kNone) continue;
-    const uint32_t r = find_root(parent, (uint32_t)i);
-    atomicAdd(&size[r], 1u);
+    if (ld_parent(parent, (uint32_t)i) == kNone) continue;
+    const uint32_t r = find_root_halving(parent, (uint32_t)i);
+    atomicMin(&parent[i], r);
+  }
+}
+
+// Cluster sizes (parents flattened): one add per site onto its root, aggregated over the
+// wavefront first (lanes with the same root add once, by their lowest lane),
+// so a spanning cluster costs one atomic per wave instead of one per site.
+__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, uint32_t* size) {
+  const size_t n = (size_t)L * L;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int lane = (int)__lane_id();
+  // the loop bound is uniform over the block, so every lane joins every ballot
+  for (size_t base = (size_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const size_t i = base + threadIdx.x;
+    bool todo = i < n && parent[i] != kNone;
+    const uint32_t r = todo ? parent[i] : 0u;
+    uint64_t left = __ballot(todo);
+    while (left) {
+      const int leader = __builtin_ctzll(left);
+      const uint32_t rl = __shfl(r, leader);
+      const uint64_t same = __ballot(todo && r == rl);
+      if (lane == leader) atomicAdd(&size[rl], (unsigned)__popcll(same));
+      if (todo && r == rl) todo = false;
+      left &= ~same;
+    }
   }
 }
 
@@ -270,6 +300,7 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int species, const Ccl
   const int g = grid_for(n, 256);
   hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
   hipLaunchKernelGGL(ccl_merge, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  hipLaunchKernelGGL(ccl_flatten, dim3(g), dim3(256), 0, stream, b.parent, L);
   hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, b.size);
   hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, b.hist, b.big,
                      b.big_count, b.big_cap);

@@ -382,6 +382,7 @@ kk_status kk_batch_run(kk_batch* b) {
     kk_sim* h = b->sims[i];
     for (size_t k = 0; k < b->count_n[i]; ++k) h->accepted_base += counts[b->count_off[i] + k];
     h->t += b->sweeps[i];
+    if (b->sweeps[i]) h->epoch += 1;
     h->attempts += b->sweeps[i] * (uint64_t)h->L * (uint64_t)h->L;
     if (!is_resident(h)) h->cur ^= (int)(b->sweeps[i] & 1u);
   }

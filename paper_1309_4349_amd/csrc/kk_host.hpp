@@ -52,6 +52,10 @@ struct kk_sim {
   kk::TileConfig tile{};
   kk::CclBuffers ccl{};
   bool ccl_ready = false;
+  uint64_t epoch = 0;                    // bumped whenever the lattice may change
+  uint64_t hist_epoch = ~(uint64_t)0;    // epoch and species of the cached histogram
+  int hist_species = -1;
+  std::vector<kk_hist_entry> hist_cache;
   bool poisoned = false;
 };
 
