@@ -44,6 +44,26 @@ VALU_PEAK_GOPS = CUS * LANES * CLOCK_HZ / 1e9   # int32 lane-ops/s, one VALU op 
 #     swaps (4 direction splits, 3 + 3 shifts/xors) and counting them (2) = 13
 #     -> 56 / 8                                                              = 7.0
 OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
+# HBM-side bytes per launch of the sweep kernel on this workload, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes recorded in
+# profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
+# a plain copy kernel of known size).  Valid only for the kernel sources that
+# were profiled: the line reports null once they change.
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "feac2554374964d4", "tile": (16, 128, 2),
+                    "bytes_per_launch": 10927278}
+KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1309_4349_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 BYTES_PER_ATTEMPT_BITS = 0.25   # read + write one bit per site per sweep
 BYTES_PER_ATTEMPT_INT8 = 2.0
 
@@ -174,7 +194,9 @@ def main():
         a = torch.ones(n, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            b.copy_(a)            # device-to-device copy (runtime copy kernel)
+        for _ in range(3):
+            torch.neg(a, out=b)   # elementwise kernel: reads and writes n * 4 bytes
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 4}))
         return
@@ -211,8 +233,15 @@ def main():
     ops = OPS_PER_ATTEMPT * attempts_per_launch / per_launch_s / 1e9
     hbm = BYTES_PER_ATTEMPT_BITS * attempts_per_launch / per_launch_s / 1e9
     tw, th, ku = sim.get_tile()
-    roofline = {"bound": "alu", "achieved": round(ops, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
-                "frac": round(ops / VALU_PEAK_GOPS, 4), "traffic": None,
+    traffic = None
+    if (kernel_sources_sha() == PROFILED_TRAFFIC["sources_sha256_prefix"]
+            and (tw, th, ku) == PROFILED_TRAFFIC["tile"] and job.L == 4096):
+        traffic = PROFILED_TRAFFIC["bytes_per_launch"]
+    roofline = {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
+                "unit": "TOP/s (32-bit VALU lane-ops)",
+                "frac": round(ops / VALU_PEAK_GOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes_per_launch": int(BYTES_PER_ATTEMPT_BITS * attempts_per_launch),
                 "kernel": f"halo_kernel<bitpacked, {tw}, {ku}>",
                 "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
                 "ops_per_attempt": OPS_PER_ATTEMPT,
