@@ -11,6 +11,7 @@ histogram of species 1.  The line also carries:
     workload on this host;
   * batched -- aggregate attempts/s of the batch engine against the same
     replicas run one after another through the plain path;
+  * grid_400 -- the 12-run 400x400 grid batched, histograms every 1000 sweeps;
   * serving -- p50/p99 latency, served and offered attempts/s of the job
     server replaying the Poisson job trace, saturated and below saturation.
 
@@ -105,7 +106,10 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int):
     sites = sum(j.L * j.L for j in jobs)
     b = kk.Batch(jobs)
     info = b.info()
-    b.run()   # warm-up run (also compiles nothing: the library is prebuilt)
+    tw, th, tms = b.autotune(10)
+    info["tile_words"], info["tile_rows"] = tw, th
+    log(f"[bench] batch autotune: tiles of at most {tw} words x {th} rows ({tms:.3f} ms per sweep)")
+    b.run()   # warm-up run
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run()
@@ -132,6 +136,52 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int):
             "sites": sites, "batched_sweeps": sweeps, "batched_attempts_per_s": batched_rate,
             "batched_s": tb, "plain_sweeps_per_replica": plain_sweeps, "plain_attempts_per_s": plain_rate,
             "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
+
+
+def grid_400(rounds: int, every: int):
+    """The 12-run 400x400 grid (3 compositions x 4 omegas, int8) advanced together
+    in one batch, with every run's species-1 cluster histogram taken every
+    `every` sweeps, against the same runs advanced one after another."""
+    import torch
+
+    from paper_1309_4349_amd import kk
+    from paper_1309_4349_amd import workloads as wl
+
+    jobs = wl.grid_400(sweeps=every)
+    sites = sum(j.L * j.L for j in jobs)
+    b = kk.Batch(jobs)
+    tw, th, _ = b.autotune(5)
+    b.run()
+    for i in range(len(jobs)):
+        b.sim(i).cluster_hist(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        b.run()
+        for i in range(len(jobs)):
+            b.sim(i).cluster_hist(1)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    rate = sites * every * rounds / tb
+    sims = [kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout) for j in jobs]
+    for s in sims:
+        s.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.sweep(every)
+        s.cluster_hist(1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    plain = sites * every / tp
+    log(f"[bench] 400^2 grid: batched {rate:.3e} attempts/s (tiles <= {tw}x{th}), one after another {plain:.3e}")
+    return {"workload": "12 runs of 400x400 int8, x in {0.3,0.5,0.7} x omega in {0.3,0.6,0.9,1.2}, "
+                        f"histogram of every run every {every} sweeps",
+            "batched_attempts_per_s": rate, "rounds": rounds, "sweeps_per_round": every,
+            "tile_words": tw, "tile_rows": th, "sequential_attempts_per_s": plain, "speedup": rate / plain}
 
 
 def serving(n_saturated: int, n_light: int, light_rate: float, chunk: int):
@@ -166,6 +216,7 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=10_000, help="sweeps per replica in the batch run")
     ap.add_argument("--batch-plain-sweeps", type=int, default=500,
                     help="sweeps per replica for the one-at-a-time plain baseline")
+    ap.add_argument("--grid-rounds", type=int, default=5, help="rounds of 1000 sweeps for the 400^2 grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the job-server trace replay")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the saturated serving trace")
     ap.add_argument("--serve-light-jobs", type=int, default=60, help="jobs of the below-saturation trace")
@@ -255,6 +306,10 @@ def main():
     if not args.no_batch:
         batched = batched_vs_plain(args.batch_sweeps, args.batch_plain_sweeps)
 
+    grid = None
+    if not args.no_batch:
+        grid = grid_400(args.grid_rounds, 1000)
+
     served = None
     if not args.no_serve:
         served = serving(args.serve_jobs, args.serve_light_jobs, args.serve_light_rate, args.serve_chunk)
@@ -278,6 +333,8 @@ def main():
     }
     if batched is not None:
         line["batched"] = batched
+    if grid is not None:
+        line["grid_400"] = grid
     if served is not None:
         line["serving"] = served
     print(json.dumps(line), flush=True)

@@ -129,6 +129,18 @@ kk_status kk_info(kk_sim *h, uint32_t *L, uint32_t *layout);
 kk_status kk_set_tile(kk_sim *h, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread);
 kk_status kk_get_tile(kk_sim *h, uint32_t *tile_words, uint32_t *tile_rows, uint32_t *units_per_thread);
 
+/* Autotune the sweep tile: time every candidate (the cyclic tile when it
+ * fits; halo tiles 1, 2, 4, 8 or 16 words wide and 32 to 256 rows high; one
+ * or two units per thread) over trial_sweeps sweeps (0 = 20) after a short
+ * warm-up, keep the fastest on this handle and use it as the default tile of
+ * handles created later in this process with the same L and layout.  The
+ * trials run on the handle's own buffers; its lattice, sweep counter and
+ * counters are restored exactly afterwards (results never depend on the tile).
+ * Outputs (any may be NULL): the chosen tile as kk_get_tile reports it and
+ * its time per sweep in microseconds.  Blocking. */
+kk_status kk_autotune(kk_sim *h, uint32_t trial_sweeps, uint32_t *tile_words, uint32_t *tile_rows,
+                      uint32_t *units_per_thread, double *us_per_sweep);
+
 /* The handle's HIP stream (hipStream_t as void*) for callers that order or time
  * their own work against it. */
 kk_status kk_stream(kk_sim *h, void **stream_out);
@@ -158,7 +170,7 @@ typedef struct {
     double composition;  /* fraction of type 1, in [0, 1] */
     double omega_kT;     /* interaction omega / kT, finite */
     uint64_t seed;       /* Philox key */
-    uint64_t sweeps;     /* sweeps this replica makes on every kk_batch_run */
+    uint64_t sweeps;     /* sweeps this replica makes on every kk_batch_run (at most 2^31 - 1) */
 } kk_replica;
 
 /* Create n replicas (each placed as kk_create would) on one device; hip_stream
@@ -171,6 +183,17 @@ kk_status kk_batch_run(kk_batch *b);
 /* Borrow replica i's handle for queries (kk_get_lattice, kk_energy,
  * kk_cluster_hist, kk_stats, ...).  The batch owns it: do not destroy it. */
 kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
+
+/* Autotune the tiles of the tiled replicas: time whole batch runs of
+ * trial_sweeps sweeps (0 = 10) for maximum tile sizes of 16 or 8 words by 128,
+ * 64 or 32 rows (smaller tiles give more workgroups when the batch holds
+ * little work, larger ones less halo work), keep the fastest and re-plan.
+ * Every replica's lattice, sweep counter and counters are restored exactly
+ * after the trials.  Outputs (any may be NULL): the chosen maximum tile width
+ * (words) and height (rows) and the best trial's milliseconds per sweep.
+ * Blocking. */
+kk_status kk_batch_autotune(kk_batch *b, uint32_t trial_sweeps, uint32_t *tile_words, uint32_t *tile_rows,
+                            double *ms_per_sweep);
 
 /* How the batch runs: resident replicas, tiled replicas, tile jobs per sweep. */
 kk_status kk_batch_info(kk_batch *b, size_t *n_resident, size_t *n_tiled, size_t *n_tile_jobs);

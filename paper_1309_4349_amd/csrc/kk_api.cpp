@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -52,8 +53,19 @@ bool cyclic_fits(int L) {
   return (L % 32) == 0 && (size_t)(L / 2) * (size_t)(L / 32) <= (size_t)2 * max_threads(2);
 }
 
+// Tiles chosen by kk_autotune, per (L, layout), for the rest of the process.
+std::mutex g_tuned_mu;
+std::map<std::pair<int, int>, TileConfig> g_tuned;
+
 void default_tile(int L, int layout, TileConfig* tc) {
-  (void)layout;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find({L, layout});
+    if (it != g_tuned.end()) {
+      *tc = it->second;
+      return;
+    }
+  }
   if (cyclic_fits(L)) {
     tc->cyclic = true;
     tc->tww = L / 32;
@@ -635,6 +647,102 @@ kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32
   if (!tile_valid(h->L, tc, &why)) return set_error(KK_EINVAL, "invalid tile: %s", why.c_str());
   h->tile = tc;
   return reset_partials(h);
+}
+
+kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, uint32_t* tile_rows,
+                      uint32_t* units_per_thread, double* us_per_sweep) {
+  KK_GUARD(h);
+  if (trial_sweeps == 0) trial_sweeps = 20;
+  if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
+  const int L = h->L;
+  // candidates: the cyclic tile when it fits, and halo tiles of the compiled widths
+  std::vector<TileConfig> cands;
+  for (int ku = 1; ku <= 2; ++ku) {
+    TileConfig tc;
+    tc.ku = ku;
+    std::string why;
+    if (cyclic_fits(L)) {
+      tc.cyclic = true;
+      tc.tww = L / 32;
+      tc.th = L;
+      if (tile_valid(L, tc, &why)) cands.push_back(tc);
+    }
+    for (int tww : {16, 8, 4, 2, 1}) {
+      if (tww > (L + 31) / 32) continue;
+      for (int th : {32, 64, 128, 256}) {
+        tc.cyclic = false;
+        tc.tww = tww;
+        tc.th = std::min(th, L);
+        bool dup = false;
+        for (const TileConfig& c : cands)
+          dup |= !c.cyclic && c.tww == tc.tww && c.th == tc.th && c.ku == tc.ku;
+        if (!dup && tile_valid(L, tc, &why)) cands.push_back(tc);
+      }
+    }
+  }
+  // save the state; trials run on the live buffers and everything is restored
+  uint64_t sw0 = 0, att0 = 0, acc0 = 0;
+  kk_status st = kk_stats(h, &sw0, &att0, &acc0);
+  if (st != KK_OK) return st;
+  const int cur0 = h->cur;
+  const TileConfig orig = h->tile;
+  const size_t bytes = lattice_bytes(h);
+  void* save = nullptr;
+  st = dmalloc(h, &save, bytes);
+  if (st != KK_OK) return st;
+  auto restore = [&](const TileConfig& keep) -> kk_status {
+    h->tile = keep;
+    kk_status s2 = reset_partials(h);
+    hipError_t e = hipMemcpyAsync(h->lat[cur0], save, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(save);
+    if (e != hipSuccess) {
+      h->poisoned = true;
+      return set_error(KK_EDEVICE, "autotune restore: %s", hipGetErrorString(e));
+    }
+    h->cur = cur0;
+    h->t = sw0;
+    h->attempts = att0;
+    h->accepted_base = acc0;  // the partials were just zeroed
+    h->epoch += 1;
+    return s2;
+  };
+  hipError_t e = hipMemcpyAsync(save, h->lat[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(save);
+    h->poisoned = true;
+    return set_error(KK_EDEVICE, "autotune save: %s", hipGetErrorString(e));
+  }
+  TileConfig best = orig;
+  double best_us = 1e300;
+  for (const TileConfig& tc : cands) {
+    h->tile = tc;
+    st = reset_partials(h);
+    if (st == KK_OK) st = enqueue_sweeps(h, 2, nullptr, nullptr);  // warm-up
+    double ms = 0.0;
+    uint64_t nl = 0;
+    if (st == KK_OK) st = enqueue_sweeps(h, trial_sweeps, &ms, &nl);
+    if (st != KK_OK) {
+      (void)restore(orig);
+      return st;
+    }
+    const double us = ms * 1e3 / trial_sweeps;
+    if (us < best_us) {
+      best_us = us;
+      best = tc;
+    }
+  }
+  st = restore(best);
+  if (st != KK_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[{L, h->layout}] = best;
+  }
+  if (tile_words) *tile_words = best.cyclic ? 0u : (uint32_t)best.tww;
+  if (tile_rows) *tile_rows = (uint32_t)best.th;
+  if (units_per_thread) *units_per_thread = (uint32_t)best.ku;
+  if (us_per_sweep) *us_per_sweep = best_us;
+  return KK_OK;
 }
 
 kk_status kk_get_tile(kk_sim* h, uint32_t* tile_words, uint32_t* tile_rows, uint32_t* units_per_thread) {

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <vector>
 
@@ -35,6 +36,8 @@ struct kk_batch {
   std::vector<kk_sim*> sims;
   std::vector<uint64_t> sweeps;
   bool own_sims = true;
+  int tile_th = kBatchTh;        // largest tile height of tiled replicas (rows, even)
+  int tile_tww = kBatchMaxTww;   // largest tile width of tiled replicas (words)
   // streams and events, created once
   hipStream_t sA = nullptr, sB = nullptr;  // resident launch; uploads and joins
   bool own_sB = false;
@@ -51,8 +54,6 @@ struct kk_batch {
   std::vector<hipGraphExec_t> tg_exec;
   std::vector<int> tg_k;          // sweep launches per replay of each group's graph
   SweepParams* d_params = nullptr;
-  void** d_bufs = nullptr;
-  unsigned long long* d_nsw = nullptr;
   BatchTileJob* d_jobs = nullptr;
   int njobs = 0;
   int* d_res = nullptr;
@@ -84,12 +85,9 @@ void clear_plan(kk_batch* b) {
   b->tg_exec.clear();
   b->tg_graph.clear();
   b->tg_k.clear();
-  for (void* p : {(void*)b->d_params, (void*)b->d_bufs, (void*)b->d_nsw, (void*)b->d_jobs, (void*)b->d_res,
-                  (void*)b->d_ctl, (void*)b->d_counts})
+  for (void* p : {(void*)b->d_params, (void*)b->d_jobs, (void*)b->d_res, (void*)b->d_ctl, (void*)b->d_counts})
     if (p) (void)hipFree(p);
   b->d_params = nullptr;
-  b->d_bufs = nullptr;
-  b->d_nsw = nullptr;
   b->d_jobs = nullptr;
   b->d_res = nullptr;
   b->d_ctl = nullptr;
@@ -140,8 +138,9 @@ kk_status make_streams(kk_batch* b, void* hip_stream) {
   return KK_OK;
 }
 
-// Geometry of a replica's batch launch (resident: whole lattice; tiled: fixed tile).
-void batch_geometry(const kk_sim* h, bool resident, SweepParams* p) {
+// Geometry of a replica's batch launch (resident: whole lattice; tiled: tiles
+// of at most max_tww words by max_th rows).
+void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, SweepParams* p) {
   TileConfig tc;
   if (resident) {
     tc.cyclic = true;
@@ -151,8 +150,8 @@ void batch_geometry(const kk_sim* h, bool resident, SweepParams* p) {
     // tiles that cover the lattice exactly: balanced widths of at most
     // kBatchMaxTww words and balanced heights of at most kBatchTh rows
     const int W = (h->L + 31) / 32;
-    const int tx = (W + kBatchMaxTww - 1) / kBatchMaxTww;
-    const int ty = (h->L + kBatchTh - 1) / kBatchTh;
+    const int tx = (W + max_tww - 1) / max_tww;
+    const int ty = (h->L + max_th - 1) / max_th;
     tc.cyclic = false;
     tc.tww = (W + tx - 1) / tx;
     tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
@@ -178,7 +177,7 @@ kk_status batch_plan(kk_batch* b) {
     kk_sim* h = b->sims[i];
     const bool res = is_resident(h);
     SweepParams p{};
-    batch_geometry(h, res, &p);
+    batch_geometry(h, res, b->tile_tww, b->tile_th, &p);
     const size_t tiles = res ? 1 : (size_t)p.tiles_x * (size_t)((h->L + p.th - 1) / p.th);
     b->count_off.push_back(b->ncounts);
     b->count_n.push_back(tiles);
@@ -221,8 +220,6 @@ kk_status batch_plan(kk_batch* b) {
                    [&](int a, int c) { return b->sims[a]->L > b->sims[c]->L; });
   kk_status st = KK_OK;
   if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
-  if (st == KK_OK) st = device_alloc((void**)&b->d_bufs, 2 * n * sizeof(void*));
-  if (st == KK_OK) st = device_alloc((void**)&b->d_nsw, n * sizeof(unsigned long long));
   if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * kMaxTileGroups);
   if (st == KK_OK) st = device_alloc((void**)&b->d_counts, b->ncounts * sizeof(unsigned long long));
   if (st == KK_OK && b->njobs) st = device_alloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchTileJob));
@@ -244,8 +241,7 @@ kk_status batch_plan(kk_batch* b) {
     if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e));
     for (int r = 0; r < k; ++r)
-      (void)launch_batch_tiles(b->d_params, b->d_bufs, b->d_nsw, b->d_jobs + b->tg_off[g], b->tg_n[g],
-                               b->d_ctl + 2 * g, s);
+      (void)launch_batch_tiles(b->d_params, b->d_jobs + b->tg_off[g], b->tg_n[g], b->d_ctl + 2 * g, s);
     e = hipStreamEndCapture(s, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     b->tg_graph.push_back(graph);
@@ -332,30 +328,27 @@ kk_status kk_batch_run(kk_batch* b) {
   const size_t n = b->sims.size();
   if (n == 0) return KK_OK;
   std::vector<SweepParams> params(n);
-  std::vector<void*> bufs(2 * n);
-  std::vector<unsigned long long> nsw(n);
+  std::vector<uint64_t> nsw(n);
   for (size_t i = 0; i < n; ++i) {
     kk_sim* h = b->sims[i];
     if (h->poisoned) return set_error(KK_ESTATE, "replica %zu poisoned", i);
     if (h->t + b->sweeps[i] >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "sweep counter overflow");
+    if (b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per replica per run");
     const bool res = is_resident(h);
-    if (res && b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per run");
     SweepParams& p = params[i];
-    batch_geometry(h, res, &p);
+    batch_geometry(h, res, b->tile_tww, b->tile_th, &p);
     p.t0 = h->t;
     p.accepted = b->d_counts + b->count_off[i];
-    bufs[2 * i] = h->lat[h->cur];
-    bufs[2 * i + 1] = h->lat[h->cur ^ 1];
-    p.src = p.dst = h->lat[h->cur];
-    p.nsweeps = (int)std::min<uint64_t>(b->sweeps[i], 0x7FFFFFFFull);
+    // resident replicas sweep in place; tiled ones ping-pong src -> dst -> src ...
+    p.src = h->lat[h->cur];
+    p.dst = res ? h->lat[h->cur] : h->lat[h->cur ^ 1];
+    p.nsweeps = (int)b->sweeps[i];
     nsw[i] = b->sweeps[i];
   }
   // every replica's own stream has finished its earlier work (placement, queries)
   for (kk_sim* h : b->sims)
     if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
   KB_HIP(hipMemcpyAsync(b->d_params, params.data(), n * sizeof(SweepParams), hipMemcpyHostToDevice, b->sB));
-  KB_HIP(hipMemcpyAsync(b->d_bufs, bufs.data(), 2 * n * sizeof(void*), hipMemcpyHostToDevice, b->sB));
-  KB_HIP(hipMemcpyAsync(b->d_nsw, nsw.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
   KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * kMaxTileGroups, b->sB));
   KB_HIP(hipEventRecord(b->ev_upload, b->sB));
@@ -386,6 +379,101 @@ kk_status kk_batch_run(kk_batch* b) {
     h->attempts += b->sweeps[i] * (uint64_t)h->L * (uint64_t)h->L;
     if (!is_resident(h)) h->cur ^= (int)(b->sweeps[i] & 1u);
   }
+  return KK_OK;
+}
+
+kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_words, uint32_t* tile_rows,
+                            double* ms_per_sweep) {
+  if (!b) return set_error(KK_EINVAL, "NULL batch");
+  if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  if (trial_sweeps == 0) trial_sweeps = 10;
+  if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
+  const size_t n = b->sims.size();
+  // save every replica: lattice, counters, buffer parity
+  struct Saved {
+    void* lat;
+    size_t bytes;
+    uint64_t t, attempts, accepted;
+    int cur;
+  };
+  std::vector<Saved> saved(n);
+  auto free_saved = [&]() {
+    for (Saved& sv : saved)
+      if (sv.lat) (void)hipFree(sv.lat);
+  };
+  for (size_t i = 0; i < n; ++i) {
+    kk_sim* h = b->sims[i];
+    Saved& sv = saved[i];
+    sv.lat = nullptr;
+    sv.bytes = h->layout == kLayoutBits ? (size_t)h->L * (size_t)(h->L / 32) * 4 : (size_t)h->L * h->L;
+    uint64_t sw = 0;
+    kk_status st = kk_stats(h, &sw, &sv.attempts, &sv.accepted);
+    if (st == KK_OK) st = device_alloc(&sv.lat, sv.bytes);
+    if (st != KK_OK) {
+      free_saved();
+      return st;
+    }
+    sv.t = h->t;
+    sv.cur = h->cur;
+    KB_HIP(hipMemcpyAsync(sv.lat, h->lat[h->cur], sv.bytes, hipMemcpyDeviceToDevice, h->stream));
+    KB_HIP(hipStreamSynchronize(h->stream));
+  }
+  auto restore_all = [&]() -> kk_status {
+    for (size_t i = 0; i < n; ++i) {
+      kk_sim* h = b->sims[i];
+      const Saved& sv = saved[i];
+      h->cur = sv.cur;
+      KB_HIP(hipMemcpyAsync(h->lat[h->cur], sv.lat, sv.bytes, hipMemcpyDeviceToDevice, h->stream));
+      KB_HIP(hipStreamSynchronize(h->stream));
+      h->t = sv.t;
+      h->attempts = sv.attempts;
+      // the handle's own tile partials are untouched by batch runs: the total
+      // is accepted_base + partials, so put back the saved difference
+      uint64_t sw = 0, att = 0, acc = 0;
+      kk_status st = kk_stats(h, &sw, &att, &acc);
+      if (st != KK_OK) return st;
+      h->accepted_base -= acc - sv.accepted;
+      h->epoch += 1;
+    }
+    return KK_OK;
+  };
+  const std::vector<uint64_t> sweeps0 = b->sweeps;
+  const int th0 = b->tile_th, tw0 = b->tile_tww;
+  int best_th = th0, best_tw = tw0;
+  double best_ms = 1e300;
+  kk_status st = KK_OK;
+  for (int tw : {kBatchMaxTww, kBatchMaxTww / 2}) {
+    for (int th : {kBatchTh, kBatchTh / 2, kBatchTh / 4}) {
+      b->tile_th = th;
+      b->tile_tww = tw;
+      st = batch_replan(b, b->sims, std::vector<uint64_t>(n, trial_sweeps));
+      if (st == KK_OK) st = kk_batch_run(b);  // warm-up (also checks the plan)
+      double ms = 0.0;
+      if (st == KK_OK) {
+        const auto t0 = std::chrono::steady_clock::now();
+        st = kk_batch_run(b);
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      const kk_status rs = restore_all();
+      if (st == KK_OK) st = rs;
+      if (st != KK_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_th = th;
+        best_tw = tw;
+      }
+    }
+    if (st != KK_OK) break;
+  }
+  free_saved();
+  b->tile_th = st == KK_OK ? best_th : th0;
+  b->tile_tww = st == KK_OK ? best_tw : tw0;
+  const kk_status ps = batch_replan(b, b->sims, sweeps0);
+  if (st == KK_OK) st = ps;
+  if (st != KK_OK) return st;
+  if (tile_words) *tile_words = (uint32_t)best_tw;
+  if (tile_rows) *tile_rows = (uint32_t)best_th;
+  if (ms_per_sweep) *ms_per_sweep = best_ms / trial_sweeps;
   return KK_OK;
 }
 

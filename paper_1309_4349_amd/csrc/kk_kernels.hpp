@@ -33,15 +33,16 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
 // Batch kernels.  Tiled replicas: one workgroup per (replica, tile) job and one
 // launch per sweep; the sweep index lives in ctl[0] and the last workgroup to
 // finish advances it (ctl[1] counts finished workgroups), so a captured
-// graph of launches can be replayed.  Resident replicas (L % 32 == 0,
+// graph of launches can be replayed.  A replica runs p.nsweeps sweeps from
+// p.t0, ping-ponging between p.src (its lattice at the start) and p.dst.  Resident replicas (L % 32 == 0,
 // 2 <= L/32 <= kResidentMaxC): one launch, one workgroup per replica running
 // all of its sweeps with the whole lattice in LDS.
 constexpr int kBatchMaxTww = 16, kBatchTh = 128, kBatchThreads = 768;
 struct BatchTileJob {
   int rep, tile;
 };
-hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const unsigned long long* nsw,
-                              const BatchTileJob* jobs, int njobs, unsigned* ctl, hipStream_t stream);
+hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
+                              hipStream_t stream);
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
                                  hipStream_t stream);
 constexpr int kResidentMaxC = 9;

@@ -882,30 +882,34 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p
 // ---------------------------------------------------------------------------
 // Batch kernels
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepParams* reps, void* const* bufs,
-                                                                   const unsigned long long* nsw,
-                                                                   const BatchTileJob* jobs, unsigned* ctl) {
+__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
+                                                                   unsigned* ctl) {
   extern __shared__ uint32_t S[];
+  // the sweep index and the job are independent loads; the replica's
+  // parameters (sweep count and both buffers included) follow the job
   const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const BatchTileJob job = jobs[blockIdx.x];
-  if (s < nsw[job.rep]) {
-    SweepParams p = reps[job.rep];
-    p.src = bufs[2 * job.rep + (s & 1u)];
-    p.dst = bufs[2 * job.rep + ((s + 1u) & 1u)];
+  SweepParams p = reps[job.rep];
+  if (s < (unsigned)p.nsweeps) {
+    if (s & 1u) {  // p.src holds the lattice at the start of the run, p.dst the other buffer
+      const void* t = p.src;
+      p.src = p.dst;
+      p.dst = const_cast<void*>(t);
+    }
     p.t0 += s;
     unsigned count;
     if (p.layout == kLayoutBits) count = halo_tile_sweep<kLayoutBits, 0, 2>(S, p, job.tile);
     else count = halo_tile_sweep<kLayoutInt8, 0, 2>(S, p, job.tile);
     add_block_count(S + p.R * kFlexST, count, p.accepted + job.tile);
   }
-  // the last workgroup to finish advances the sweep index for the next launch
+  // The last workgroup to arrive advances the sweep index for the next launch.
+  // Device-scope atomics order the hand-off; the lattice writes reach the next
+  // launch through the kernel boundary, so no fence is needed here.
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned prev = atomicAdd(&ctl[1], 1u);
     if (prev == gridDim.x - 1) {
-      ctl[1] = 0u;
-      ctl[0] = s + 1u;
-      __threadfence();
+      __hip_atomic_store(&ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl[0], s + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -1006,10 +1010,10 @@ size_t batch_tile_lds_bytes() {
 
 size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * sizeof(uint32_t); }
 
-hipError_t launch_batch_tiles(const SweepParams* reps, void* const* bufs, const unsigned long long* nsw,
-                              const BatchTileJob* jobs, int njobs, unsigned* ctl, hipStream_t stream) {
-  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchThreads), batch_tile_lds_bytes(), stream, reps, bufs,
-                     nsw, jobs, ctl);
+hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchThreads), batch_tile_lds_bytes(), stream, reps, jobs,
+                     ctl);
   return hipGetLastError();
 }
 

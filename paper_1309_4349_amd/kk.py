@@ -21,9 +21,9 @@ _LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPAC
 
 EXPORTS = [
     "kk_create", "kk_create_ex", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
-    "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile",
+    "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
-    "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_destroy",
+    "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
     "kk_server_destroy",
@@ -104,12 +104,14 @@ def load(path: str = LIB_PATH):
         "kk_info": [P, u32p, u32p],
         "kk_set_tile": [P, U32, U32, U32],
         "kk_get_tile": [P, u32p, u32p, u32p],
+        "kk_autotune": [P, U32, u32p, u32p, u32p, dp],
         "kk_stream": [P, PP],
         "kk_sweep_timed": [P, U64, dp, u64p],
         "kk_batch_create": [PP, ctypes.POINTER(Replica), ctypes.c_size_t, P],
         "kk_batch_run": [P],
         "kk_batch_sim": [P, ctypes.c_size_t, PP],
         "kk_batch_info": [P, szp, szp, szp],
+        "kk_batch_autotune": [P, U32, u32p, u32p, dp],
         "kk_server_create": [PP, ctypes.POINTER(ServerConfig)],
         "kk_server_now": [P, dp],
         "kk_server_submit": [P, ctypes.POINTER(Replica), D, u64p],
@@ -238,6 +240,14 @@ class Sim:
         _check(load().kk_get_tile(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
+    def autotune(self, trial_sweeps: int = 20) -> Tuple[int, int, int, float]:
+        """Time the candidate tiles, keep the fastest; returns (words, rows, units_per_thread, us_per_sweep)."""
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        us = ctypes.c_double()
+        _check(load().kk_autotune(self._h, trial_sweeps, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                  ctypes.byref(us)))
+        return a.value, b.value, c.value, us.value
+
     def stream(self) -> int:
         p = ctypes.c_void_p()
         _check(load().kk_stream(self._h, ctypes.byref(p)))
@@ -280,6 +290,13 @@ class Batch:
         _check(load().kk_batch_sim(self._h, i, ctypes.byref(h)))
         j = self.jobs[i]
         return _Borrowed(h, j.L, float(j.omega), j.seed)
+
+    def autotune(self, trial_sweeps: int = 10) -> Tuple[int, int, float]:
+        """Pick the tile size of the tiled replicas by timing; returns (words, rows, ms_per_sweep)."""
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        ms = ctypes.c_double()
+        _check(load().kk_batch_autotune(self._h, trial_sweeps, ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms)))
+        return a.value, b.value, ms.value
 
     def info(self):
         a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()

@@ -77,3 +77,26 @@ def test_batch_standing_replica_table_prefix():
         assert np.array_equal(b.sim(i).get_lattice(), alone.get_lattice()), i
         alone.close()
     b.close()
+
+
+def test_batch_autotune_restores_state():
+    jobs = mixed_jobs()
+    say("case batch autotune over", len(jobs), "mixed replicas")
+    b = kk.Batch(jobs)
+    b.run()
+    before = [(b.sim(i).get_lattice(), b.sim(i).stats(), b.sim(i).energy()) for i in range(len(jobs))]
+    words, rows, ms = b.autotune(3)
+    assert words in (8, 16) and rows in (32, 64, 128) and ms > 0
+    for i in range(len(jobs)):
+        lat, st, e = before[i]
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), lat), i
+        assert s.stats() == st and s.energy() == e, i
+    b.run()   # continues as if never tuned
+    for i, j in enumerate(jobs):
+        alone = kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout)
+        alone.sweep(2 * j.sweeps)
+        assert np.array_equal(b.sim(i).get_lattice(), alone.get_lattice()), i
+        assert b.sim(i).stats() == alone.stats(), i
+        alone.close()
+    b.close()
