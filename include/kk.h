@@ -185,9 +185,10 @@ kk_status kk_batch_run(kk_batch *b);
 kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
 /* Autotune the tiles of the tiled replicas: time whole batch runs of
- * trial_sweeps sweeps (0 = 10) for maximum tile sizes of 16 or 8 words by 128,
- * 64 or 32 rows (smaller tiles give more workgroups when the batch holds
- * little work, larger ones less halo work), keep the fastest and re-plan.
+ * trial_sweeps sweeps (0 = 10) for maximum tile sizes (words x rows) of
+ * 8 x 128, 16 x 64, 8 x 64, 16 x 32 and 4 x 128 (smaller tiles give more
+ * workgroups when the batch holds little work, larger ones less halo work),
+ * keep the fastest and re-plan.
  * Every replica's lattice, sweep counter and counters are restored exactly
  * after the trials.  Outputs (any may be NULL): the chosen maximum tile width
  * (words) and height (rows) and the best trial's milliseconds per sweep.

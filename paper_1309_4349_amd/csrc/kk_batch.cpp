@@ -37,7 +37,7 @@ struct kk_batch {
   std::vector<uint64_t> sweeps;
   bool own_sims = true;
   int tile_th = kBatchTh;        // largest tile height of tiled replicas (rows, even)
-  int tile_tww = kBatchMaxTww;   // largest tile width of tiled replicas (words)
+  int tile_tww = kBatchMaxTww / 2;  // largest tile width of tiled replicas (words)
   // streams and events, created once
   hipStream_t sA = nullptr, sB = nullptr;  // resident launch; uploads and joins
   bool own_sB = false;
@@ -151,10 +151,14 @@ void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, Swe
     // kBatchMaxTww words and balanced heights of at most kBatchTh rows
     const int W = (h->L + 31) / 32;
     const int tx = (W + max_tww - 1) / max_tww;
-    const int ty = (h->L + max_th - 1) / max_th;
+    int ty = (h->L + max_th - 1) / max_th;
     tc.cyclic = false;
     tc.tww = (W + tx - 1) / tx;
     tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
+    while (!batch_tile_fits(tc.tww, tc.th)) {  // more rows of tiles until one fits a workgroup
+      ++ty;
+      tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
+    }
   }
   tc.ku = 2;
   tile_geometry(h->L, tc, p);
@@ -442,28 +446,27 @@ kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_w
   int best_th = th0, best_tw = tw0;
   double best_ms = 1e300;
   kk_status st = KK_OK;
-  for (int tw : {kBatchMaxTww, kBatchMaxTww / 2}) {
-    for (int th : {kBatchTh, kBatchTh / 2, kBatchTh / 4}) {
-      b->tile_th = th;
-      b->tile_tww = tw;
-      st = batch_replan(b, b->sims, std::vector<uint64_t>(n, trial_sweeps));
-      if (st == KK_OK) st = kk_batch_run(b);  // warm-up (also checks the plan)
-      double ms = 0.0;
-      if (st == KK_OK) {
-        const auto t0 = std::chrono::steady_clock::now();
-        st = kk_batch_run(b);
-        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      }
-      const kk_status rs = restore_all();
-      if (st == KK_OK) st = rs;
-      if (st != KK_OK) break;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_th = th;
-        best_tw = tw;
-      }
+  static const int cand[][2] = {{8, 128}, {16, 64}, {8, 64}, {16, 32}, {4, 128}};
+  for (const auto& c : cand) {
+    const int tw = c[0], th = c[1];
+    b->tile_th = th;
+    b->tile_tww = tw;
+    st = batch_replan(b, b->sims, std::vector<uint64_t>(n, trial_sweeps));
+    if (st == KK_OK) st = kk_batch_run(b);  // warm-up (also checks the plan)
+    double ms = 0.0;
+    if (st == KK_OK) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = kk_batch_run(b);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+    const kk_status rs = restore_all();
+    if (st == KK_OK) st = rs;
     if (st != KK_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_th = th;
+      best_tw = tw;
+    }
   }
   free_saved();
   b->tile_th = st == KK_OK ? best_th : th0;

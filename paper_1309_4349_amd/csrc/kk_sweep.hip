@@ -882,7 +882,7 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p
 // ---------------------------------------------------------------------------
 // Batch kernels
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
+__global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
                                                                    unsigned* ctl) {
   extern __shared__ uint32_t S[];
   // the sweep index and the job are independent loads; the replica's
@@ -1012,7 +1012,7 @@ size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * si
 
 hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
                               hipStream_t stream) {
-  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchThreads), batch_tile_lds_bytes(), stream, reps, jobs,
+  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchTileThreads), batch_tile_lds_bytes(), stream, reps, jobs,
                      ctl);
   return hipGetLastError();
 }
