@@ -156,10 +156,10 @@ void kk_destroy(kk_sim *h);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent replicas (uneven L, composition, omega, seed)
- * advanced together.  Replicas with L % 32 == 0 and 64 <= L <= 288 run in one
- * persistent launch with the whole lattice held in LDS; the others run as
- * one launch per sweep over all their tiles, replayed from a captured HIP
- * graph.  A replica's result equals what kk_create_ex + kk_sweep gives for the
+ * advanced together.  Replicas with L % 32 == 0 and 64 <= L <= 288 run in
+ * persistent launches (one for L <= 160, one for the rest) with the whole
+ * lattice held in LDS; the others run as one launch per sweep over all their
+ * tiles, replayed from captured HIP graphs.  A replica's result equals what kk_create_ex + kk_sweep gives for the
  * same parameters (no replica or slot index enters any random number).
  * ------------------------------------------------------------------------- */
 typedef struct kk_batch kk_batch;

@@ -6,10 +6,10 @@
 // workgroup, which keeps the lattice in LDS for all of its sweeps.  The others
 // are "tiled": they are split into a few groups of equal work; for each group
 // every sweep is one launch over all of the group's halo tiles, and those
-// launches are captured in a HIP graph that is replayed.  The resident launch
-// and the groups run concurrently, each on its own stream (few streams in
-// all: the device multiplexes streams over a small number of hardware queues,
-// and two streams sharing one queue serialise).  No slot or replica index
+// launches are captured in a HIP graph that is replayed.  Resident replicas
+// of at most kResidentSmallMaxC words per row run in 256-thread workgroups
+// (three per CU), larger ones in 768-thread workgroups; the two resident
+// launches and the tile groups run concurrently, each on its own stream.  No slot or replica index
 // enters any random counter, so every replica ends exactly where kk_sweep
 // would have left it.
 //
@@ -39,13 +39,15 @@ struct kk_batch {
   int tile_th = kBatchTh;        // largest tile height of tiled replicas (rows, even)
   int tile_tww = kBatchMaxTww / 2;  // largest tile width of tiled replicas (words)
   // streams and events, created once
-  hipStream_t sA = nullptr, sB = nullptr;  // resident launch; uploads and joins
+  hipStream_t sA = nullptr, sB = nullptr;  // large resident launch; uploads and joins
+  hipStream_t sC = nullptr;                 // small resident launch
   bool own_sB = false;
-  hipEvent_t ev_upload = nullptr, ev_res = nullptr;
+  hipEvent_t ev_upload = nullptr, ev_res = nullptr, ev_small = nullptr;
   hipStream_t tg_stream[kMaxTileGroups] = {};
   hipEvent_t tg_done[kMaxTileGroups] = {};
   // plan, rebuilt by batch_plan
   std::vector<int> resident, tiled;
+  size_t n_small = 0;  // resident[0, n_small) run in the small kernel, the rest in the large one
   std::vector<size_t> count_off, count_n;
   size_t ncounts = 0;
   std::vector<int> tg_off, tg_n;  // tiled groups: slices of the tile-job table
@@ -57,7 +59,7 @@ struct kk_batch {
   BatchTileJob* d_jobs = nullptr;
   int njobs = 0;
   int* d_res = nullptr;
-  size_t res_lds = 0;
+  size_t res_lds = 0, small_lds = 0;
   unsigned* d_ctl = nullptr;
   unsigned long long* d_counts = nullptr;
   bool poisoned = false;
@@ -102,6 +104,8 @@ void clear_plan(kk_batch* b) {
   b->job_rep.clear();
   b->njobs = 0;
   b->res_lds = 0;
+  b->small_lds = 0;
+  b->n_small = 0;
 }
 
 void free_batch(kk_batch* b) {
@@ -115,7 +119,9 @@ void free_batch(kk_batch* b) {
   }
   if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
   if (b->ev_res) (void)hipEventDestroy(b->ev_res);
+  if (b->ev_small) (void)hipEventDestroy(b->ev_small);
   if (b->sA) (void)hipStreamDestroy(b->sA);
+  if (b->sC) (void)hipStreamDestroy(b->sC);
   if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
 }
 
@@ -128,8 +134,10 @@ kk_status make_streams(kk_batch* b, void* hip_stream) {
     b->own_sB = true;
   }
   if ((e = hipStreamCreateWithFlags(&b->sA, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->sC, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess)
+      (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->ev_small, hipEventDisableTiming)) != hipSuccess)
     return set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e));
   for (int g = 0; g < kMaxTileGroups; ++g)
     if ((e = hipStreamCreateWithFlags(&b->tg_stream[g], hipStreamNonBlocking)) != hipSuccess ||
@@ -188,12 +196,23 @@ kk_status batch_plan(kk_batch* b) {
     b->ncounts += tiles;
     if (res) {
       b->resident.push_back((int)i);
-      b->res_lds = std::max(b->res_lds, batch_resident_lds_bytes(h->L));
+      if (h->L / 32 <= kResidentSmallMaxC) b->small_lds = std::max(b->small_lds, batch_resident_lds_bytes(h->L));
+      else b->res_lds = std::max(b->res_lds, batch_resident_lds_bytes(h->L));
     } else {
       b->tiled.push_back((int)i);
     }
   }
-  // longest-processing-time split of the tiled replicas by work per run
+  // small resident replicas first (their own launch), then the large ones,
+  // each part widest first (the widest run longest)
+  std::stable_sort(b->resident.begin(), b->resident.end(), [&](int a, int c) {
+    const bool sa = b->sims[a]->L / 32 <= kResidentSmallMaxC, sc = b->sims[c]->L / 32 <= kResidentSmallMaxC;
+    if (sa != sc) return sa;
+    return b->sims[a]->L > b->sims[c]->L;
+  });
+  for (int i : b->resident) b->n_small += b->sims[i]->L / 32 <= kResidentSmallMaxC;
+  // longest-processing-time split of the tiled replicas by work per run: three
+  // groups beside the resident launches (measured best; one more group or one
+  // fewer only adds queue sharing or tail idle), four without them
   const int ngroups = (int)std::min<size_t>(b->resident.empty() ? kMaxTileGroups : kMaxTileGroups - 1,
                                             b->tiled.size());
   std::vector<std::vector<int>> groups(ngroups);
@@ -219,9 +238,6 @@ kk_status batch_plan(kk_batch* b) {
   }
   b->njobs = (int)jobs.size();
   for (const BatchTileJob& j : jobs) b->job_rep.push_back(j.rep);
-  // resident replicas: one launch, widest lattices first (they run longest)
-  std::stable_sort(b->resident.begin(), b->resident.end(),
-                   [&](int a, int c) { return b->sims[a]->L > b->sims[c]->L; });
   kk_status st = KK_OK;
   if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
   if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * kMaxTileGroups);
@@ -356,9 +372,15 @@ kk_status kk_batch_run(kk_batch* b) {
   KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
   KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * kMaxTileGroups, b->sB));
   KB_HIP(hipEventRecord(b->ev_upload, b->sB));
-  if (!b->resident.empty()) {
+  const size_t n_large = b->resident.size() - b->n_small;
+  if (b->n_small) {
+    KB_HIP(hipStreamWaitEvent(b->sC, b->ev_upload, 0));
+    KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->n_small, b->small_lds, true, b->sC));
+    KB_HIP(hipEventRecord(b->ev_small, b->sC));
+  }
+  if (n_large) {
     KB_HIP(hipStreamWaitEvent(b->sA, b->ev_upload, 0));
-    KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->resident.size(), b->res_lds, b->sA));
+    KB_HIP(launch_batch_resident(b->d_params, b->d_res + b->n_small, (int)n_large, b->res_lds, false, b->sA));
     KB_HIP(hipEventRecord(b->ev_res, b->sA));
   }
   for (size_t g = 0; g < b->tg_exec.size(); ++g) {
@@ -370,7 +392,8 @@ kk_status kk_batch_run(kk_batch* b) {
     for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->tg_exec[g], s));
     KB_HIP(hipEventRecord(b->tg_done[g], s));
   }
-  if (!b->resident.empty()) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
+  if (b->n_small) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_small, 0));
+  if (n_large) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
   for (size_t g = 0; g < b->tg_exec.size(); ++g) KB_HIP(hipStreamWaitEvent(b->sB, b->tg_done[g], 0));
   KB_HIP(hipStreamSynchronize(b->sB));
   std::vector<unsigned long long> counts(b->ncounts);
@@ -499,6 +522,7 @@ void kk_batch_destroy(kk_batch* b) {
   if (!b) return;
   if (b->sB) (void)hipStreamSynchronize(b->sB);
   if (b->sA) (void)hipStreamSynchronize(b->sA);
+  if (b->sC) (void)hipStreamSynchronize(b->sC);
   for (int g = 0; g < kMaxTileGroups; ++g)
     if (b->tg_stream[g]) (void)hipStreamSynchronize(b->tg_stream[g]);
   free_batch(b);

@@ -50,9 +50,11 @@ struct BatchTileJob {
 };
 hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
                               hipStream_t stream);
-hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
+// small: the 256-thread kernel for replicas of at most kResidentSmallMaxC words per row.
+hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
                                  hipStream_t stream);
 constexpr int kResidentMaxC = 9;
+constexpr int kResidentSmallMaxC = 5, kResidentSmallThreads = 256;
 size_t batch_tile_lds_bytes();
 size_t batch_resident_lds_bytes(int L);
 

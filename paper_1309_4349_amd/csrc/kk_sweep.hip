@@ -936,6 +936,22 @@ __global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const
   add_block_count(S + (p.R + 4) * 36, count, p.accepted);
 }
 
+// Small resident replicas (L <= 32 * kResidentSmallMaxC: at most 512 units)
+// in 256-thread workgroups, three per CU.
+__global__ __launch_bounds__(kResidentSmallThreads, 3) void batch_resident_small_kernel(const SweepParams* reps,
+                                                                                       const int* ids) {
+  extern __shared__ uint32_t S[];
+  const SweepParams p = reps[ids[blockIdx.x]];
+  unsigned count;
+  switch (p.C) {
+    case 2: count = cyc_sweeps<0, 2, 2>(S, p); break;
+    case 3: count = cyc_sweeps<0, 3, 2>(S, p); break;
+    case 4: count = cyc_sweeps<0, 4, 2>(S, p); break;
+    default: count = cyc_sweeps<0, 5, 2>(S, p); break;
+  }
+  add_block_count(S + (p.R + 4) * 36, count, p.accepted);
+}
+
 }  // namespace
 
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream) {
@@ -1017,9 +1033,13 @@ hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs,
   return hipGetLastError();
 }
 
-hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes,
+hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
                                  hipStream_t stream) {
-  hipLaunchKernelGGL(batch_resident_all_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
+  if (small)
+    hipLaunchKernelGGL(batch_resident_small_kernel, dim3(n), dim3(kResidentSmallThreads), lds_bytes, stream, reps,
+                       ids);
+  else
+    hipLaunchKernelGGL(batch_resident_all_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
   return hipGetLastError();
 }
 
