@@ -185,8 +185,8 @@ kk_status kk_batch_run(kk_batch *b);
 kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
 /* Autotune the tiles of the tiled replicas: time whole batch runs of
- * trial_sweeps sweeps (0 = 10) for maximum tile sizes (words x rows) of
- * 8 x 128, 16 x 64, 8 x 64, 16 x 32 and 4 x 128 (smaller tiles give more
+ * trial_sweeps sweeps (0 = 10) for tiles (words x at most rows) of
+ * 8 x 128, 16 x 84, 8 x 64 and 16 x 42 (smaller tiles give more
  * workgroups when the batch holds little work, larger ones less halo work),
  * keep the fastest and re-plan.
  * Every replica's lattice, sweep counter and counters are restored exactly

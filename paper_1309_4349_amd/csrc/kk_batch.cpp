@@ -147,7 +147,7 @@ kk_status make_streams(kk_batch* b, void* hip_stream) {
 }
 
 // Geometry of a replica's batch launch (resident: whole lattice; tiled: tiles
-// of at most max_tww words by max_th rows).
+// of max_tww (8 or 16) words by at most max_th rows).
 void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, SweepParams* p) {
   TileConfig tc;
   if (resident) {
@@ -155,13 +155,11 @@ void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, Swe
     tc.tww = h->L / 32;
     tc.th = h->L;
   } else {
-    // tiles that cover the lattice exactly: balanced widths of at most
-    // kBatchMaxTww words and balanced heights of at most kBatchTh rows
-    const int W = (h->L + 31) / 32;
-    const int tx = (W + max_tww - 1) / max_tww;
+    // tiles max_tww (8 or 16) words wide, the last column possibly ragged, and
+    // balanced heights of at most max_th rows that fit one workgroup
     int ty = (h->L + max_th - 1) / max_th;
     tc.cyclic = false;
-    tc.tww = (W + tx - 1) / tx;
+    tc.tww = max_tww;
     tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
     while (!batch_tile_fits(tc.tww, tc.th)) {  // more rows of tiles until one fits a workgroup
       ++ty;
@@ -469,7 +467,7 @@ kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_w
   int best_th = th0, best_tw = tw0;
   double best_ms = 1e300;
   kk_status st = KK_OK;
-  static const int cand[][2] = {{8, 128}, {16, 64}, {8, 64}, {16, 32}, {4, 128}};
+  static const int cand[][2] = {{8, 128}, {16, 84}, {8, 64}, {16, 42}};
   for (const auto& c : cand) {
     const int tw = c[0], th = c[1];
     b->tile_th = th;

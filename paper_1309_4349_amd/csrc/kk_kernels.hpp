@@ -39,11 +39,12 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
 // all of its sweeps with the whole lattice in LDS.
 constexpr int kBatchMaxTww = 16, kBatchTh = 128, kBatchThreads = 768;
 // Tiled replicas run in 512-thread workgroups (two per CU), two units per
-// thread: a tile of tww words by th rows fits when its (th + 28) / 2 computed
-// row pairs times tww + 2 words stay within 1024 units.
+// thread, in tiles 8 or 16 words wide: a tile of tww words by th rows fits
+// when its (th + 28) / 2 computed row pairs times tww + 2 words stay within
+// 1024 units.
 constexpr int kBatchTileThreads = 512;
 constexpr bool batch_tile_fits(int tww, int th) {
-  return tww >= 1 && tww <= kBatchMaxTww && th >= 2 && th <= kBatchTh && ((th + 28) / 2) * (tww + 2) <= 2 * kBatchTileThreads;
+  return (tww == 8 || tww == 16) && th >= 2 && th <= kBatchTh && ((th + 28) / 2) * (tww + 2) <= 2 * kBatchTileThreads;
 }
 struct BatchTileJob {
   int rep, tile;

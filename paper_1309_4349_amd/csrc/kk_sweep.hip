@@ -588,19 +588,15 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
 // the second unit hides behind the first.
 // One sweep of tile `tile` of the lattice described by p (halo mode).
 // Returns this thread's accepted count for the tile interior.
-// TWW == 0 selects a runtime tile width (p.tww <= kFlexMaxTww) with a fixed
-// row stride, for tiles sized to fit a lattice exactly.
-constexpr int kFlexMaxTww = 16;
-constexpr int kFlexST = HaloGeom<kFlexMaxTww>::ST;
 
 template <int LAYOUT, int TWW, int KU>
 __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
-  const int C = TWW > 0 ? HaloGeom<(TWW > 0 ? TWW : 1)>::C : p.tww + 2;
-  constexpr int ST = TWW > 0 ? HaloGeom<(TWW > 0 ? TWW : 1)>::ST : kFlexST;
+  constexpr int C = HaloGeom<TWW>::C;
+  constexpr int ST = HaloGeom<TWW>::ST;
   const int CP = C + 2;       // staged words per row (the pads included)
   constexpr int NSTG = 6;     // staged global words per thread
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-  const int TW = TWW > 0 ? TWW : p.tww;
+  constexpr int TW = TWW;
   const int X0 = tx * TW * 32, Y0 = ty * p.th;
   const int XL = X0 - 32, YT = Y0 - 16;
   const int xend = min(X0 + TW * 32, p.L), yend = min(Y0 + p.th, p.L);
@@ -897,10 +893,18 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
       p.dst = const_cast<void*>(t);
     }
     p.t0 += s;
+    // compile-time tile width (8 or 16 words: immediate, bank-conflict-free
+    // LDS offsets) chosen per replica by a uniform switch; a replica's last
+    // tile column may be ragged
     unsigned count;
-    if (p.layout == kLayoutBits) count = halo_tile_sweep<kLayoutBits, 0, 2>(S, p, job.tile);
-    else count = halo_tile_sweep<kLayoutInt8, 0, 2>(S, p, job.tile);
-    add_block_count(S + p.R * kFlexST, count, p.accepted + job.tile);
+    if (p.layout == kLayoutBits) {
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, 2>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutBits, 16, 2>(S, p, job.tile);
+    } else {
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, 2>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutInt8, 16, 2>(S, p, job.tile);
+    }
+    add_block_count(S + p.R * HaloGeom<16>::ST, count, p.accepted + job.tile);
   }
   // The last workgroup to arrive advances the sweep index for the next launch.
   // Device-scope atomics order the hand-off; the lattice writes reach the next
@@ -1020,8 +1024,8 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
 namespace kk {
 
 size_t batch_tile_lds_bytes() {
-  const int R = kBatchTh + 32;
-  return ((size_t)R * kFlexST + 16 + R + kBatchMaxTww + 2) * sizeof(uint32_t);
+  const int R = kBatchTh + 32;  // the widest tile has the largest stride
+  return ((size_t)R * HaloGeom<kBatchMaxTww>::ST + 16 + R + kBatchMaxTww + 2) * sizeof(uint32_t);
 }
 
 size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * sizeof(uint32_t); }
