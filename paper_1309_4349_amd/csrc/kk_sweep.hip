@@ -208,19 +208,41 @@ __device__ __forceinline__ void gen_planes_at(const SweepParams& p, int y, int x
   gen_planes(p, y, Xw, t, pl);
 }
 
+// Three-input bitwise function with a truth table built from the operand
+// patterns a = 0xF0, b = 0xCC, c = 0xAA (one v_bitop3_b32).
+#define KK_TA 0xF0u
+#define KK_TB 0xCCu
+#define KK_TC 0xAAu
+#define KK_TT(expr) ((unsigned)((expr) & 0xFFu))
+template <unsigned TT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+// a ? b : c, per bit
+__device__ __forceinline__ uint32_t bsel(uint32_t a, uint32_t b, uint32_t c) {
+  return bop3<KK_TT((KK_TA & KK_TB) | (~KK_TA & KK_TC))>(a, b, c);
+}
+constexpr unsigned kXor3 = KK_TT(KK_TA ^ KK_TB ^ KK_TC);
+constexpr unsigned kMaj3 = KK_TT((KK_TA & KK_TB) | (KK_TA & KK_TC) | (KK_TB & KK_TC));
+
 // 10-bit (u < K) and (u == K) over bit-sliced u, planes[2] = MSB .. planes[11] = LSB,
-// processed from the least significant bit: lt' = maj(~u_k, K_k, lt).
+// for a K that is the same on every lane.  Less-than is the borrow chain of
+// u - K from the least significant bit, lt' = maj(~u_k, K_k, lt), one
+// three-input op per bit; equality is the AND of u_k XNOR K_k, one XNOR per bit
+// and a tree of three-input ANDs.
 __device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& lt, uint32_t& eq) {
-  uint32_t l = 0u, e = 0xFFFFFFFFu;
+  constexpr unsigned kBorrow = KK_TT((~KK_TA & KK_TB) | (~KK_TA & KK_TC) | (KK_TB & KK_TC));
+  constexpr unsigned kAnd3 = KK_TT(KK_TA & KK_TB & KK_TC);
+  uint32_t l = 0u, x[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
     const uint32_t u = pl[11 - k];
     const uint32_t kb = 0u - ((K >> k) & 1u);
-    l = maj3(~u, kb, l);
-    e = e & ~(u ^ kb);
+    l = bop3<kBorrow>(u, kb, l);
+    x[k] = ~(u ^ kb);
   }
   lt = l;
-  eq = e;
+  eq = bop3<kAnd3>(bop3<kAnd3>(x[0], x[1], x[2]), bop3<kAnd3>(x[3], x[4], x[5]), bop3<kAnd3>(x[6], x[7], x[8])) & x[9];
 }
 
 template <bool CYC>
@@ -444,22 +466,6 @@ __device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& 
   if (p.acc.hi[2] < 1024u) cmp10(pl, p.acc.hi[2], q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
 }
 
-// Three-input bitwise function with a truth table built from the operand
-// patterns a = 0xF0, b = 0xCC, c = 0xAA (one v_bitop3_b32).
-#define KK_TA 0xF0u
-#define KK_TB 0xCCu
-#define KK_TC 0xAAu
-#define KK_TT(expr) ((unsigned)((expr) & 0xFFu))
-template <unsigned TT>
-__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
-}
-// a ? b : c, per bit
-__device__ __forceinline__ uint32_t bsel(uint32_t a, uint32_t b, uint32_t c) {
-  return bop3<KK_TT((KK_TA & KK_TB) | (~KK_TA & KK_TC))>(a, b, c);
-}
-constexpr unsigned kXor3 = KK_TT(KK_TA ^ KK_TB ^ KK_TC);
-constexpr unsigned kMaj3 = KK_TT((KK_TA & KK_TB) | (KK_TA & KK_TC) | (KK_TB & KK_TC));
 
 // Decide the exchanges of the centres in `cmask` of one 32-site word.
 // v: the word (0), its west/east neighbours (1, 2), the same three in the
