@@ -664,7 +664,13 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
       row_rand(pl, p, rr[k][h]);
     }
   }
-  const uint32_t perm = class_order(p.k0, p.k1, t);
+  // the class order is the same for the whole workgroup: the first wave
+  // computes it into the word after the column table
+  uint32_t* perm_slot = reinterpret_cast<uint32_t*>(xtab + C);
+  if (threadIdx.x < 64) {
+    const uint32_t pm = class_order(p.k0, p.k1, t);
+    if (threadIdx.x == 0) *perm_slot = pm;
+  }
 #pragma unroll
   for (int j = 0; j < NSTG; ++j) {
     const int i = threadIdx.x + j * blockDim.x;
@@ -672,6 +678,7 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     if (i < total) S[r * ST + w] = stg[j];
   }
   __syncthreads();
+  const uint32_t perm = *perm_slot;
 
   unsigned count = 0;
 #pragma unroll 1
@@ -808,7 +815,7 @@ __device__ __forceinline__ unsigned cyc_phase(uint32_t* S, const SweepParams& p,
 // Whole lattice in one workgroup, p.nsweeps sweeps from p.t0.  Returns the
 // thread's accepted count.
 template <int LAYOUT, int C, int KU>
-__device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p) {
+__device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p, uint32_t* perm_slot) {
   constexpr int ST = CycGeom<C>::ST;
   const int R = p.R;  // == L
   const int L = p.L;
@@ -855,8 +862,14 @@ __device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p
         row_rand(pl, p, rr[k][h]);
       }
     }
-    const uint32_t perm = class_order(p.k0, p.k1, t);
+    // one wave computes the sweep's class order; every wave has read the
+    // previous one (right after the previous sweep's first barrier)
+    if (threadIdx.x < 64) {
+      const uint32_t pm = class_order(p.k0, p.k1, t);
+      if (threadIdx.x == 0) *perm_slot = pm;
+    }
     __syncthreads();  // staging or the previous sweep complete
+    const uint32_t perm = *perm_slot;
 #pragma unroll 1
     for (int ph = 0; ph < 8; ++ph) {
       const uint32_t cls = (perm >> (4 * ph)) & 0xFu;
@@ -876,7 +889,7 @@ __device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p
 template <int LAYOUT, int C, int KU>
 __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p) {
   extern __shared__ uint32_t S[];
-  const unsigned count = cyc_sweeps<LAYOUT, C, KU>(S, p);
+  const unsigned count = cyc_sweeps<LAYOUT, C, KU>(S, p, S + (p.R + 4) * CycGeom<C>::ST + 16);
   add_block_count(S + (p.R + 4) * CycGeom<C>::ST, count, p.accepted);
 }
 
@@ -932,16 +945,17 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
 __global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const SweepParams* reps, const int* ids) {
   extern __shared__ uint32_t S[];
   const SweepParams p = reps[ids[blockIdx.x]];
+  uint32_t* slot = S + (p.R + 4) * 36 + 16;  // past the reduction area
   unsigned count;
   switch (p.C) {
-    case 2: count = cyc_sweeps<0, 2, 2>(S, p); break;
-    case 3: count = cyc_sweeps<0, 3, 2>(S, p); break;
-    case 4: count = cyc_sweeps<0, 4, 2>(S, p); break;
-    case 5: count = cyc_sweeps<0, 5, 2>(S, p); break;
-    case 6: count = cyc_sweeps<0, 6, 2>(S, p); break;
-    case 7: count = cyc_sweeps<0, 7, 2>(S, p); break;
-    case 8: count = cyc_sweeps<0, 8, 2>(S, p); break;
-    default: count = cyc_sweeps<0, 9, 2>(S, p); break;
+    case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
+    case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
+    case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
+    case 5: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
+    case 6: count = cyc_sweeps<0, 6, 2>(S, p, slot); break;
+    case 7: count = cyc_sweeps<0, 7, 2>(S, p, slot); break;
+    case 8: count = cyc_sweeps<0, 8, 2>(S, p, slot); break;
+    default: count = cyc_sweeps<0, 9, 2>(S, p, slot); break;
   }
   add_block_count(S + (p.R + 4) * 36, count, p.accepted);
 }
@@ -952,12 +966,13 @@ __global__ __launch_bounds__(kResidentSmallThreads, 3) void batch_resident_small
                                                                                        const int* ids) {
   extern __shared__ uint32_t S[];
   const SweepParams p = reps[ids[blockIdx.x]];
+  uint32_t* slot = S + (p.R + 4) * 36 + 16;  // past the reduction area
   unsigned count;
   switch (p.C) {
-    case 2: count = cyc_sweeps<0, 2, 2>(S, p); break;
-    case 3: count = cyc_sweeps<0, 3, 2>(S, p); break;
-    case 4: count = cyc_sweeps<0, 4, 2>(S, p); break;
-    default: count = cyc_sweeps<0, 5, 2>(S, p); break;
+    case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
+    case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
+    case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
+    default: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
   }
   add_block_count(S + (p.R + 4) * 36, count, p.accepted);
 }
@@ -971,7 +986,7 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
   if (cyclic && p.C >= 2 && p.C <= 11) {
 #define KK_CYC(LY, CC)                                                                            \
   do {                                                                                            \
-    const size_t cl = ((size_t)(p.R + 4) * CycGeom<CC>::ST + 16) * sizeof(uint32_t);              \
+    const size_t cl = ((size_t)(p.R + 4) * CycGeom<CC>::ST + 17) * sizeof(uint32_t);              \
     if (ku == 1) hipLaunchKernelGGL((cyc_kernel<LY, CC, 1>), grid, block, cl, stream, p);         \
     else hipLaunchKernelGGL((cyc_kernel<LY, CC, 2>), grid, block, cl, stream, p);                 \
   } while (0)
@@ -993,7 +1008,7 @@ hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, i
   if (!cyclic && (p.tww == 1 || p.tww == 2 || p.tww == 4 || p.tww == 8 || p.tww == 16)) {
 #define KK_HALO(LY, TW)                                                                                  \
   do {                                                                                                   \
-    const size_t hl = ((size_t)p.R * HaloGeom<TW>::ST + 16 + p.R + HaloGeom<TW>::C) * sizeof(uint32_t);  \
+    const size_t hl = ((size_t)p.R * HaloGeom<TW>::ST + 17 + p.R + HaloGeom<TW>::C) * sizeof(uint32_t);  \
     if (ku == 1) hipLaunchKernelGGL((halo_kernel<LY, TW, 1>), grid, block, hl, stream, p);               \
     else hipLaunchKernelGGL((halo_kernel<LY, TW, 2>), grid, block, hl, stream, p);                       \
   } while (0)
@@ -1031,10 +1046,10 @@ namespace kk {
 
 size_t batch_tile_lds_bytes() {
   const int R = kBatchTh + 32;  // the widest tile has the largest stride
-  return ((size_t)R * HaloGeom<kBatchMaxTww>::ST + 16 + R + kBatchMaxTww + 2) * sizeof(uint32_t);
+  return ((size_t)R * HaloGeom<kBatchMaxTww>::ST + 17 + R + kBatchMaxTww + 2) * sizeof(uint32_t);
 }
 
-size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 16) * sizeof(uint32_t); }
+size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 17) * sizeof(uint32_t); }
 
 hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
                               hipStream_t stream) {
