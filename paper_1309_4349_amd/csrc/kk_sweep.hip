@@ -458,12 +458,20 @@ struct RowRand {
   uint32_t d0, d1, lt0, lt1, lt2, eq0, eq1, eq2;
 };
 
+// The threshold prefixes pass through an empty asm so that their per-bit masks
+// are rebuilt (a few scalar ops) at every use instead of being hoisted and
+// kept live across the kernel, which overflows the scalar registers.
+__device__ __forceinline__ uint32_t opaque_sgpr(uint32_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 __device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& p, RowRand& q) {
   q.d0 = pl[0];
   q.d1 = pl[1];
-  if (p.acc.hi[0] < 1024u) cmp10(pl, p.acc.hi[0], q.lt0, q.eq0); else { q.lt0 = 0xFFFFFFFFu; q.eq0 = 0u; }
-  if (p.acc.hi[1] < 1024u) cmp10(pl, p.acc.hi[1], q.lt1, q.eq1); else { q.lt1 = 0xFFFFFFFFu; q.eq1 = 0u; }
-  if (p.acc.hi[2] < 1024u) cmp10(pl, p.acc.hi[2], q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
+  if (p.acc.hi[0] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[0]), q.lt0, q.eq0); else { q.lt0 = 0xFFFFFFFFu; q.eq0 = 0u; }
+  if (p.acc.hi[1] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[1]), q.lt1, q.eq1); else { q.lt1 = 0xFFFFFFFFu; q.eq1 = 0u; }
+  if (p.acc.hi[2] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[2]), q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
 }
 
 
@@ -692,14 +700,21 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     __syncthreads();
   }
 
-  // write the interior back
+  // write the interior back (a full-width tile divides by a constant)
   const int iw = (xend - X0 + 31) / 32, ih = yend - Y0;
-  for (int i = threadIdx.x; i < iw * ih; i += blockDim.x) {
-    const int rr2 = i / iw, ww = i - rr2 * iw;
-    const int x0 = X0 + 32 * ww;
-    const int nb = min(32, xend - x0);
-    const uint32_t val = S[(16 + rr2) * ST + 1 + ww + 1];
-    store_word<LAYOUT>(p, Y0 + rr2, x0, nb == 32 ? val : (val & ((1u << nb) - 1u)), nb);
+  if (xend - X0 == TW * 32) {
+    for (int i = threadIdx.x; i < TW * ih; i += blockDim.x) {
+      const int rr2 = i / TW, ww = i - rr2 * TW;
+      store_word<LAYOUT>(p, Y0 + rr2, X0 + 32 * ww, S[(16 + rr2) * ST + 1 + ww + 1], 32);
+    }
+  } else {
+    for (int i = threadIdx.x; i < iw * ih; i += blockDim.x) {
+      const int rr2 = i / iw, ww = i - rr2 * iw;
+      const int x0 = X0 + 32 * ww;
+      const int nb = min(32, xend - x0);
+      const uint32_t val = S[(16 + rr2) * ST + 1 + ww + 1];
+      store_word<LAYOUT>(p, Y0 + rr2, x0, nb == 32 ? val : (val & ((1u << nb) - 1u)), nb);
+    }
   }
 
   return count;
