@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     lib = kk.load()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert set(_declared()) <= set(kk.EXPORTS) | {n for n in _declared() if n.startswith("kk_batch") or n.startswith("kk_serve")}
+    assert set(_declared()) == set(kk.EXPORTS)
 
 
 @pytest.mark.parametrize("L,x,w,layout", [
@@ -54,3 +54,33 @@ def test_null_handle_calls_are_rejected():
     n = ctypes.c_size_t()
     assert lib.kk_cluster_hist(None, 1, None, 0, ctypes.byref(n)) == kk.KK_EINVAL
     lib.kk_destroy(None)
+
+
+def test_null_handles_of_the_batch_server_and_tuner_calls_are_rejected():
+    lib = kk.load()
+    w, r, u = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    d = ctypes.c_double()
+    n = ctypes.c_size_t()
+    assert lib.kk_autotune(None, 5, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u), ctypes.byref(d)) == kk.KK_EINVAL
+    assert lib.kk_batch_create(None, None, 0, None) == kk.KK_EINVAL
+    h = ctypes.c_void_p(1)
+    assert lib.kk_batch_create(ctypes.byref(h), None, 0, None) == kk.KK_EINVAL and h.value is None
+    assert lib.kk_batch_run(None) == kk.KK_EINVAL
+    assert lib.kk_batch_autotune(None, 5, None, None, None) == kk.KK_EINVAL
+    assert lib.kk_batch_sim(None, 0, ctypes.byref(h)) == kk.KK_EINVAL
+    assert lib.kk_batch_info(None, None, None, None) == kk.KK_EINVAL
+    lib.kk_batch_destroy(None)
+    assert lib.kk_server_create(None, None) == kk.KK_EINVAL
+    assert lib.kk_server_now(None, ctypes.byref(d)) == kk.KK_EINVAL
+    rep = kk.Replica(64, 1, 0.5, 0.5, 1, 10)
+    jid = ctypes.c_uint64()
+    assert lib.kk_server_submit(None, ctypes.byref(rep), -1.0, ctypes.byref(jid)) == kk.KK_EINVAL
+    assert lib.kk_server_step(None, ctypes.byref(n), ctypes.byref(n)) == kk.KK_EINVAL
+    assert lib.kk_server_poll(None, None, 0, ctypes.byref(n)) == kk.KK_EINVAL
+    assert lib.kk_server_job_hist(None, 1, None, 0, ctypes.byref(n)) == kk.KK_EINVAL
+    assert lib.kk_server_job_lattice(None, 1, None, 0) == kk.KK_EINVAL
+    assert lib.kk_server_release(None, 1) == kk.KK_EINVAL
+    st = kk.ServerStats()
+    assert lib.kk_server_get_stats(None, ctypes.byref(st)) == kk.KK_EINVAL
+    lib.kk_server_destroy(None)
+    assert lib.kk_last_error()
