@@ -669,7 +669,7 @@ kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, ui
     }
     for (int tww : {16, 8, 4, 2, 1}) {
       if (tww > (L + 31) / 32) continue;
-      for (int th : {32, 64, 128, 256}) {
+      for (int th : {32, 48, 64, 96, 128, 192, 256}) {
         tc.cyclic = false;
         tc.tww = tww;
         tc.th = std::min(th, L);
