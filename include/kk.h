@@ -131,14 +131,14 @@ kk_status kk_get_tile(kk_sim *h, uint32_t *tile_words, uint32_t *tile_rows, uint
 
 /* Autotune the sweep tile: time every candidate (the cyclic tile when it
  * fits; halo tiles 1, 2, 4, 8 or 16 words wide and 32, 48, 64, 96, 128, 192
- * or 256 rows high; one or two units per thread) over trial_sweeps sweeps
- * (0 = 20) after a short
- * warm-up, keep the fastest on this handle and use it as the default tile of
- * handles created later in this process with the same L and layout.  The
- * trials run on the handle's own buffers; its lattice, sweep counter and
- * counters are restored exactly afterwards (results never depend on the tile).
- * Outputs (any may be NULL): the chosen tile as kk_get_tile reports it and
- * its time per sweep in microseconds.  Blocking. */
+ * or 256 rows high; one or two units per thread) over trial_sweeps sweeps (0
+ * = 20) after a short warm-up, keep the fastest on this handle and use it as
+ * the default tile of handles created later in this process with the same L
+ * and layout. The trials run on the handle's own buffers; its lattice, sweep
+ * counter and counters are restored exactly afterwards (results never depend
+ * on the tile). Outputs (any may be NULL): the chosen tile as kk_get_tile
+ * reports it and its time per sweep in microseconds. Blocking.
+ */
 kk_status kk_autotune(kk_sim *h, uint32_t trial_sweeps, uint32_t *tile_words, uint32_t *tile_rows,
                       uint32_t *units_per_thread, double *us_per_sweep);
 
