@@ -4,12 +4,16 @@
 // Replicas whose whole lattice fits one workgroup (L % 32 == 0, 64 <= L <=
 // 32 * kResidentMaxC) are "resident": one persistent launch gives each its own
 // workgroup, which keeps the lattice in LDS for all of its sweeps.  The others
-// are "tiled": they are split into a few groups of equal work; for each group
-// every sweep is one launch over all of the group's halo tiles, and those
-// launches are captured in a HIP graph that is replayed.  Resident replicas
-// of at most kResidentSmallMaxC words per row run in 256-thread workgroups
-// (three per CU), larger ones in 768-thread workgroups; the two resident
-// launches and the tile groups run concurrently, each on its own stream.  No slot or replica index
+// are "tiled": they are split into a few groups of equal work, and for each
+// group every sweep is one launch over all of the group's halo tiles.
+// Resident replicas of at most kResidentSmallMaxC words per row run in
+// 256-thread workgroups (three per CU), larger ones in 768-thread workgroups.
+// One HIP graph holds a chunk of kBatchChunk sweeps of everything: a branch
+// per tile group (kBatchChunk chained launches) and a branch per resident
+// kernel (one launch of kBatchChunk sweeps), forked from and joined to one
+// stream; the graph is replayed once per chunk.  Branches of one graph run
+// concurrently, which separate streams replaying their own graphs did not
+// do here (measured).  No slot or replica index
 // enters any random counter, so every replica ends exactly where kk_sweep
 // would have left it.
 //
@@ -30,6 +34,11 @@ using namespace kk;
 
 namespace {
 constexpr int kMaxTileGroups = 4;
+// sweep hand-off words (two each): one per tile group, then the small and the
+// large resident launch
+constexpr int kCtlSlots = kMaxTileGroups + 2, kCtlSmall = kMaxTileGroups, kCtlLarge = kMaxTileGroups + 1;
+// tile workgroups that fill the device once (256 CUs, two per CU)
+constexpr size_t kFillWorkgroups = 512;
 }
 
 struct kk_batch {
@@ -42,7 +51,7 @@ struct kk_batch {
   hipStream_t sA = nullptr, sB = nullptr;  // large resident launch; uploads and joins
   hipStream_t sC = nullptr;                 // small resident launch
   bool own_sB = false;
-  hipEvent_t ev_upload = nullptr, ev_res = nullptr, ev_small = nullptr;
+  hipEvent_t ev_upload = nullptr, ev_res = nullptr;
   hipStream_t tg_stream[kMaxTileGroups] = {};
   hipEvent_t tg_done[kMaxTileGroups] = {};
   // plan, rebuilt by batch_plan
@@ -52,9 +61,9 @@ struct kk_batch {
   size_t ncounts = 0;
   std::vector<int> tg_off, tg_n;  // tiled groups: slices of the tile-job table
   std::vector<int> job_rep;       // host copy: replica of every tile job
-  std::vector<hipGraph_t> tg_graph;
-  std::vector<hipGraphExec_t> tg_exec;
-  std::vector<int> tg_k;          // sweep launches per replay of each group's graph
+  hipGraph_t graph = nullptr;     // one chunk of kBatchChunk sweeps of every branch
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_fork = nullptr;
   SweepParams* d_params = nullptr;
   BatchTileJob* d_jobs = nullptr;
   int njobs = 0;
@@ -80,13 +89,10 @@ namespace {
 bool is_resident(const kk_sim* h) { return h->L % 32 == 0 && h->L >= 64 && h->L / 32 <= kResidentMaxC; }
 
 void clear_plan(kk_batch* b) {
-  for (hipGraphExec_t ge : b->tg_exec)
-    if (ge) (void)hipGraphExecDestroy(ge);
-  for (hipGraph_t g : b->tg_graph)
-    if (g) (void)hipGraphDestroy(g);
-  b->tg_exec.clear();
-  b->tg_graph.clear();
-  b->tg_k.clear();
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
   for (void* p : {(void*)b->d_params, (void*)b->d_jobs, (void*)b->d_res, (void*)b->d_ctl, (void*)b->d_counts})
     if (p) (void)hipFree(p);
   b->d_params = nullptr;
@@ -119,7 +125,7 @@ void free_batch(kk_batch* b) {
   }
   if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
   if (b->ev_res) (void)hipEventDestroy(b->ev_res);
-  if (b->ev_small) (void)hipEventDestroy(b->ev_small);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->sA) (void)hipStreamDestroy(b->sA);
   if (b->sC) (void)hipStreamDestroy(b->sC);
   if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
@@ -137,7 +143,7 @@ kk_status make_streams(kk_batch* b, void* hip_stream) {
       (e = hipStreamCreateWithFlags(&b->sC, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&b->ev_res, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&b->ev_small, hipEventDisableTiming)) != hipSuccess)
+      (e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess)
     return set_error(KK_EDEVICE, "stream/event: %s", hipGetErrorString(e));
   for (int g = 0; g < kMaxTileGroups; ++g)
     if ((e = hipStreamCreateWithFlags(&b->tg_stream[g], hipStreamNonBlocking)) != hipSuccess ||
@@ -174,7 +180,6 @@ void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, Swe
   p->layout = h->layout;
 }
 
-int graph_launches(uint64_t max_sweeps) { return (int)std::max<uint64_t>(1, std::min<uint64_t>(max_sweeps, 64)); }
 
 // Plan the current replica set: resident list, tile jobs split into groups of
 // equal work, device tables and one captured graph per group.
@@ -208,11 +213,15 @@ kk_status batch_plan(kk_batch* b) {
     return b->sims[a]->L > b->sims[c]->L;
   });
   for (int i : b->resident) b->n_small += b->sims[i]->L / 32 <= kResidentSmallMaxC;
-  // longest-processing-time split of the tiled replicas by work per run: three
-  // groups beside the resident launches (measured best; one more group or one
-  // fewer only adds queue sharing or tail idle), four without them
-  const int ngroups = (int)std::min<size_t>(b->resident.empty() ? kMaxTileGroups : kMaxTileGroups - 1,
-                                            b->tiled.size());
+  // longest-processing-time split of the tiled replicas by work per run.  Two
+  // tile chains fill each other's launch tails when the tiles can fill the
+  // device; fewer tiles run best as one chain.  Graph branches run
+  // concurrently only up to the device's hardware queues (four): the two tile
+  // chains plus at most two resident launches stay within that (measured: a
+  // fifth branch serialises behind another).
+  size_t tile_jobs = 0;
+  for (int i : b->tiled) tile_jobs += b->count_n[i];
+  const int ngroups = (int)std::min<size_t>(tile_jobs >= kFillWorkgroups ? 2 : 1, b->tiled.size());
   std::vector<std::vector<int>> groups(ngroups);
   {
     std::vector<int> order = b->tiled;
@@ -238,7 +247,7 @@ kk_status batch_plan(kk_batch* b) {
   for (const BatchTileJob& j : jobs) b->job_rep.push_back(j.rep);
   kk_status st = KK_OK;
   if (st == KK_OK) st = device_alloc((void**)&b->d_params, n * sizeof(SweepParams));
-  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * kMaxTileGroups);
+  if (st == KK_OK) st = device_alloc((void**)&b->d_ctl, 2 * sizeof(unsigned) * kCtlSlots);
   if (st == KK_OK) st = device_alloc((void**)&b->d_counts, b->ncounts * sizeof(unsigned long long));
   if (st == KK_OK && b->njobs) st = device_alloc((void**)&b->d_jobs, jobs.size() * sizeof(BatchTileJob));
   if (st == KK_OK && !b->resident.empty()) st = device_alloc((void**)&b->d_res, b->resident.size() * sizeof(int));
@@ -250,23 +259,37 @@ kk_status batch_plan(kk_batch* b) {
   if (!b->resident.empty() && (e = hipMemcpy(b->d_res, b->resident.data(), b->resident.size() * sizeof(int),
                                              hipMemcpyHostToDevice)) != hipSuccess)
     return set_error(KK_EDEVICE, "upload ids: %s", hipGetErrorString(e));
-  // per group: a captured graph of k sweep launches over the group's tile jobs
-  for (int g = 0; g < ngroups; ++g) {
-    hipStream_t s = b->tg_stream[g];
-    const int k = graph_launches(maxsw[g]);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e));
-    for (int r = 0; r < k; ++r)
-      (void)launch_batch_tiles(b->d_params, b->d_jobs + b->tg_off[g], b->tg_n[g], b->d_ctl + 2 * g, s);
-    e = hipStreamEndCapture(s, &graph);
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    b->tg_graph.push_back(graph);
-    b->tg_exec.push_back(exec);
-    b->tg_k.push_back(k);
-    if (e != hipSuccess) return set_error(KK_EDEVICE, "graph: %s", hipGetErrorString(e));
+  // one graph: fork from tile group 0's stream, a branch per tile group and
+  // per resident launch, join back
+  const size_t n_small = b->n_small, n_large = b->resident.size() - b->n_small;
+  hipStream_t origin = b->tg_stream[0];
+  if ((e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return set_error(KK_EDEVICE, "capture: %s", hipGetErrorString(e));
+  std::vector<hipStream_t> branches;
+  for (int g = 1; g < ngroups; ++g) branches.push_back(b->tg_stream[g]);
+  if (n_small) branches.push_back(b->sC);
+  if (n_large) branches.push_back(b->sA);
+  e = hipEventRecord(b->ev_fork, origin);
+  for (hipStream_t bs : branches)
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs, b->ev_fork, 0);
+  for (int g = 0; g < ngroups && e == hipSuccess; ++g)
+    for (int r = 0; r < kBatchChunk && e == hipSuccess; ++r)
+      e = launch_batch_tiles(b->d_params, b->d_jobs + b->tg_off[g], b->tg_n[g], b->d_ctl + 2 * g, b->tg_stream[g]);
+  if (e == hipSuccess && n_small)
+    e = launch_batch_resident(b->d_params, b->d_res, (int)n_small, b->small_lds, true, b->d_ctl + 2 * kCtlSmall, b->sC);
+  if (e == hipSuccess && n_large)
+    e = launch_batch_resident(b->d_params, b->d_res + n_small, (int)n_large, b->res_lds, false,
+                              b->d_ctl + 2 * kCtlLarge, b->sA);
+  for (size_t i = 0; i < branches.size() && e == hipSuccess; ++i) {
+    e = hipEventRecord(b->tg_done[i % kMaxTileGroups], branches[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->tg_done[i % kMaxTileGroups], 0);
   }
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(origin, &graph);  // always end the capture
+  if (e == hipSuccess) e = ee;
+  b->graph = graph;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return set_error(KK_EDEVICE, "batch graph: %s", hipGetErrorString(e));
   return KK_OK;
 }
 
@@ -368,31 +391,16 @@ kk_status kk_batch_run(kk_batch* b) {
     if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
   KB_HIP(hipMemcpyAsync(b->d_params, params.data(), n * sizeof(SweepParams), hipMemcpyHostToDevice, b->sB));
   KB_HIP(hipMemsetAsync(b->d_counts, 0, b->ncounts * sizeof(unsigned long long), b->sB));
-  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * kMaxTileGroups, b->sB));
+  KB_HIP(hipMemsetAsync(b->d_ctl, 0, 2 * sizeof(unsigned) * kCtlSlots, b->sB));
   KB_HIP(hipEventRecord(b->ev_upload, b->sB));
-  const size_t n_large = b->resident.size() - b->n_small;
-  if (b->n_small) {
-    KB_HIP(hipStreamWaitEvent(b->sC, b->ev_upload, 0));
-    KB_HIP(launch_batch_resident(b->d_params, b->d_res, (int)b->n_small, b->small_lds, true, b->sC));
-    KB_HIP(hipEventRecord(b->ev_small, b->sC));
-  }
-  if (n_large) {
-    KB_HIP(hipStreamWaitEvent(b->sA, b->ev_upload, 0));
-    KB_HIP(launch_batch_resident(b->d_params, b->d_res + b->n_small, (int)n_large, b->res_lds, false, b->sA));
-    KB_HIP(hipEventRecord(b->ev_res, b->sA));
-  }
-  for (size_t g = 0; g < b->tg_exec.size(); ++g) {
-    hipStream_t s = b->tg_stream[g];
-    KB_HIP(hipStreamWaitEvent(s, b->ev_upload, 0));
-    uint64_t mx = 0;
-    for (int q = b->tg_off[g]; q < b->tg_off[g] + b->tg_n[g]; ++q) mx = std::max<uint64_t>(mx, nsw[b->job_rep[q]]);
-    const uint64_t reps = (mx + b->tg_k[g] - 1) / b->tg_k[g];
-    for (uint64_t r = 0; r < reps; ++r) KB_HIP(hipGraphLaunch(b->tg_exec[g], s));
-    KB_HIP(hipEventRecord(b->tg_done[g], s));
-  }
-  if (b->n_small) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_small, 0));
-  if (n_large) KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
-  for (size_t g = 0; g < b->tg_exec.size(); ++g) KB_HIP(hipStreamWaitEvent(b->sB, b->tg_done[g], 0));
+  // replay the chunk graph until the longest replica is done
+  uint64_t mx = 0;
+  for (size_t i = 0; i < n; ++i) mx = std::max<uint64_t>(mx, nsw[i]);
+  hipStream_t origin = b->tg_stream[0];
+  KB_HIP(hipStreamWaitEvent(origin, b->ev_upload, 0));
+  for (uint64_t r = 0; r < (mx + kBatchChunk - 1) / kBatchChunk; ++r) KB_HIP(hipGraphLaunch(b->gexec, origin));
+  KB_HIP(hipEventRecord(b->ev_res, origin));
+  KB_HIP(hipStreamWaitEvent(b->sB, b->ev_res, 0));
   KB_HIP(hipStreamSynchronize(b->sB));
   std::vector<unsigned long long> counts(b->ncounts);
   KB_HIP(hipMemcpy(counts.data(), b->d_counts, b->ncounts * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -467,7 +475,7 @@ kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_w
   int best_th = th0, best_tw = tw0;
   double best_ms = 1e300;
   kk_status st = KK_OK;
-  static const int cand[][2] = {{8, 128}, {16, 84}, {8, 64}, {16, 42}};
+  static const int cand[][2] = {{8, 128}, {16, 84}, {8, 64}, {16, 42}, {8, 32}, {8, 16}};
   for (const auto& c : cand) {
     const int tw = c[0], th = c[1];
     b->tile_th = th;

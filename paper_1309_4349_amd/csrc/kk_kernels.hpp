@@ -51,9 +51,14 @@ struct BatchTileJob {
 };
 hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
                               hipStream_t stream);
-// small: the 256-thread kernel for replicas of at most kResidentSmallMaxC words per row.
+// small: the 256-thread kernel for replicas of at most kResidentSmallMaxC words
+// per row.  A launch runs up to kBatchChunk sweeps from sweep ctl[0] of the run
+// and advances ctl[0] by kBatchChunk (see launch_batch_tiles).
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
-                                 hipStream_t stream);
+                                 unsigned* ctl, hipStream_t stream);
+// Sweeps per replay of a batch graph: kBatchChunk tile launches per tile group
+// and one resident launch of kBatchChunk sweeps.
+constexpr int kBatchChunk = 64;
 constexpr int kResidentMaxC = 9;
 constexpr int kResidentSmallMaxC = 5, kResidentSmallThreads = 256;
 size_t batch_tile_lds_bytes();

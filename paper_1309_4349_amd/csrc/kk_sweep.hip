@@ -616,6 +616,11 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
   const int xend = min(X0 + TW * 32, p.L), yend = min(Y0 + p.th, p.L);
   const int total = p.R * CP;
   const uint64_t t = p.t0;
+  // LDS words that can reach the interior: the left halo word, the interior
+  // words and one halo word past them.  In a ragged last tile the words after
+  // that behave like the zero pad of a full tile: they are neither loaded nor
+  // computed (for L % 32 != 0 they would also sit off the 32-site segment grid).
+  const int wneed = min(C, (xend - X0 + 31) / 32 + 2);
   // true (wrapped) row of every LDS row and true column of every LDS word
   int* ytab = reinterpret_cast<int*>(S + p.R * ST + 16);
   int* xtab = ytab + p.R;
@@ -631,11 +636,11 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
   for (int j = 0; j < NSTG; ++j) {
     const int i = threadIdx.x + j * blockDim.x;
     const int r = i / CP, w = i - r * CP - 1;
-    stg[j] = (i < total && w >= 0 && w < C) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
+    stg[j] = (i < total && w >= 0 && w < wneed) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
   }
   for (int i = threadIdx.x + NSTG * blockDim.x; i < total; i += blockDim.x) {
     const int r = i / CP, w = i - r * CP - 1;
-    S[r * ST + w + 1] = (w >= 0 && w < C) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
+    S[r * ST + w + 1] = (w >= 0 && w < wneed) ? load_word_at<LAYOUT>(p, ytab[r], xtab[w]) : 0u;
   }
 
   int base0[KU], yrow[KU * 2], xw[KU];  // LDS base; true row of each of the pair's rows; true x of bit 0
@@ -645,8 +650,27 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
     const int u = threadIdx.x + k * blockDim.x;
-    const bool ok = u < p.nunits;
-    const int q = ok ? u / C : 0, w = ok ? u - q * C : 0;
+    const bool in = u < p.nunits;
+    int q, wu;
+    if ((p.L & 31) == 0) {
+      q = in ? u / C : 0;
+      wu = in ? u - q * C : 0;
+    } else {
+      // off-grid lattices: the two edge words of every row gather their random
+      // planes from two or three segments; numbering them after all inner
+      // words confines that slower path to the last waves
+      const int nin = p.npairs * (C - 2);
+      if (u < nin) {
+        q = u / (C - 2);
+        wu = 1 + (u - q * (C - 2));
+      } else {
+        const int e = in ? u - nin : 0;
+        q = e >> 1;
+        wu = (e & 1) ? C - 1 : 0;
+      }
+    }
+    const bool ok = in && wu < wneed;
+    const int w = ok ? wu : 0;
     const int r0 = 2 + 2 * q;
     base0[k] = r0 * ST + w + 1;
     yrow[2 * k] = ytab[r0];
@@ -667,9 +691,13 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     for (int h = 0; h < 2; ++h) {
       const int yv = YT + r0 + h;
       imask[k][h] = (ok && yv >= Y0 && yv < yend) ? wm : 0u;
-      uint32_t pl[kPlanes];
-      gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
-      row_rand(pl, p, rr[k][h]);
+      if (ok) {
+        uint32_t pl[kPlanes];
+        gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
+        row_rand(pl, p, rr[k][h]);
+      } else {
+        rr[k][h] = RowRand{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      }
     }
   }
   // the class order is the same for the whole workgroup: the first wave
@@ -912,6 +940,21 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p
 // ---------------------------------------------------------------------------
 // Batch kernels
 // ---------------------------------------------------------------------------
+// Sweep hand-off of the batch kernels, which a captured graph replays: a
+// launch starts at sweep ctl[0] of the run and the last workgroup to finish
+// advances it by `step` for the next launch (ctl[1] counts finished
+// workgroups).  Device-scope atomics order the hand-off; lattice writes reach
+// the next launch through the kernel boundary, so no fence is needed.
+__device__ __forceinline__ void batch_advance(unsigned* ctl, unsigned s, unsigned step) {
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(&ctl[1], 1u);
+    if (prev == gridDim.x - 1) {
+      __hip_atomic_store(&ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl[0], s + step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
                                                                    unsigned* ctl) {
   extern __shared__ uint32_t S[];
@@ -940,16 +983,7 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
     }
     add_block_count(S + p.R * HaloGeom<16>::ST, count, p.accepted + job.tile);
   }
-  // The last workgroup to arrive advances the sweep index for the next launch.
-  // Device-scope atomics order the hand-off; the lattice writes reach the next
-  // launch through the kernel boundary, so no fence is needed here.
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&ctl[1], 1u);
-    if (prev == gridDim.x - 1) {
-      __hip_atomic_store(&ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl[0], s + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  batch_advance(ctl, s, 1u);
 }
 
 // All resident replicas in one launch, one workgroup each: the width is a
@@ -957,39 +991,53 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
 // share one register allocation) and the layout is a run-time branch of the
 // staging and the final store.  The reduction area sits past the largest
 // resident lattice (rows L+4, stride <= 36).
-__global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const SweepParams* reps, const int* ids) {
+__global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const SweepParams* reps, const int* ids,
+                                                                           unsigned* ctl) {
   extern __shared__ uint32_t S[];
-  const SweepParams p = reps[ids[blockIdx.x]];
-  uint32_t* slot = S + (p.R + 4) * 36 + 16;  // past the reduction area
-  unsigned count;
-  switch (p.C) {
-    case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
-    case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
-    case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
-    case 5: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
-    case 6: count = cyc_sweeps<0, 6, 2>(S, p, slot); break;
-    case 7: count = cyc_sweeps<0, 7, 2>(S, p, slot); break;
-    case 8: count = cyc_sweeps<0, 8, 2>(S, p, slot); break;
-    default: count = cyc_sweeps<0, 9, 2>(S, p, slot); break;
+  const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  SweepParams p = reps[ids[blockIdx.x]];
+  if (s < (unsigned)p.nsweeps) {  // this launch: up to kBatchChunk sweeps from run sweep s
+    p.t0 += s;
+    p.nsweeps = min(kBatchChunk, p.nsweeps - (int)s);
+    uint32_t* slot = S + (p.R + 4) * 36 + 16;  // past the reduction area
+    unsigned count;
+    switch (p.C) {
+      case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
+      case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
+      case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
+      case 5: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
+      case 6: count = cyc_sweeps<0, 6, 2>(S, p, slot); break;
+      case 7: count = cyc_sweeps<0, 7, 2>(S, p, slot); break;
+      case 8: count = cyc_sweeps<0, 8, 2>(S, p, slot); break;
+      default: count = cyc_sweeps<0, 9, 2>(S, p, slot); break;
+    }
+    add_block_count(S + (p.R + 4) * 36, count, p.accepted);
   }
-  add_block_count(S + (p.R + 4) * 36, count, p.accepted);
+  batch_advance(ctl, s, (unsigned)kBatchChunk);
 }
 
 // Small resident replicas (L <= 32 * kResidentSmallMaxC: at most 512 units)
 // in 256-thread workgroups, three per CU.
 __global__ __launch_bounds__(kResidentSmallThreads, 3) void batch_resident_small_kernel(const SweepParams* reps,
-                                                                                       const int* ids) {
+                                                                                       const int* ids,
+                                                                                       unsigned* ctl) {
   extern __shared__ uint32_t S[];
-  const SweepParams p = reps[ids[blockIdx.x]];
-  uint32_t* slot = S + (p.R + 4) * 36 + 16;  // past the reduction area
-  unsigned count;
-  switch (p.C) {
-    case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
-    case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
-    case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
-    default: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
+  const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  SweepParams p = reps[ids[blockIdx.x]];
+  if (s < (unsigned)p.nsweeps) {
+    p.t0 += s;
+    p.nsweeps = min(kBatchChunk, p.nsweeps - (int)s);
+    uint32_t* slot = S + (p.R + 4) * 36 + 16;
+    unsigned count;
+    switch (p.C) {
+      case 2: count = cyc_sweeps<0, 2, 2>(S, p, slot); break;
+      case 3: count = cyc_sweeps<0, 3, 2>(S, p, slot); break;
+      case 4: count = cyc_sweeps<0, 4, 2>(S, p, slot); break;
+      default: count = cyc_sweeps<0, 5, 2>(S, p, slot); break;
+    }
+    add_block_count(S + (p.R + 4) * 36, count, p.accepted);
   }
-  add_block_count(S + (p.R + 4) * 36, count, p.accepted);
+  batch_advance(ctl, s, (unsigned)kBatchChunk);
 }
 
 }  // namespace
@@ -1074,12 +1122,12 @@ hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs,
 }
 
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
-                                 hipStream_t stream) {
+                                 unsigned* ctl, hipStream_t stream) {
   if (small)
     hipLaunchKernelGGL(batch_resident_small_kernel, dim3(n), dim3(kResidentSmallThreads), lds_bytes, stream, reps,
-                       ids);
+                       ids, ctl);
   else
-    hipLaunchKernelGGL(batch_resident_all_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids);
+    hipLaunchKernelGGL(batch_resident_all_kernel, dim3(n), dim3(kBatchThreads), lds_bytes, stream, reps, ids, ctl);
   return hipGetLastError();
 }
 
