@@ -86,7 +86,7 @@ def test_batch_autotune_restores_state():
     b.run()
     before = [(b.sim(i).get_lattice(), b.sim(i).stats(), b.sim(i).energy()) for i in range(len(jobs))]
     words, rows, ms = b.autotune(3)
-    assert (words, rows) in ((8, 128), (16, 84), (8, 64), (16, 42)) and ms > 0
+    assert (words, rows) in ((8, 128), (16, 84), (8, 64), (16, 42), (8, 32), (8, 16)) and ms > 0
     for i in range(len(jobs)):
         lat, st, e = before[i]
         s = b.sim(i)
@@ -99,4 +99,27 @@ def test_batch_autotune_restores_state():
         assert np.array_equal(b.sim(i).get_lattice(), alone.get_lattice()), i
         assert b.sim(i).stats() == alone.stats(), i
         alone.close()
+    b.close()
+
+
+@pytest.mark.parametrize("specs", [
+    # (L, layout, composition, omega, sweeps)
+    [(64, "int8", 0.0, 0.9, 5), (96, "bitpacked", 1.0, 0.9, 5), (320, "bitpacked", 0.5, 0.7, 0), (32, "bitpacked", 0.5, 1.1, 9)],
+    [(160, "int8", 0.5, 0.5, 70)],
+    [(64, "bitpacked", 0.4, 0.8, 3), (128, "int8", 0.6, -0.5, 130), (288, "bitpacked", 0.5, 0.88, 65)],
+    [(36, "int8", 0.5, 0.3, 65), (4, "int8", 0.5, 2.0, 7), (12, "int8", 0.25, 0.0, 11)],
+])
+def test_batch_edge_cases_match_the_oracle(specs):
+    jobs = [wl.Job(L=L, composition=x, omega=w, seed=wl.job_seed(55, i), sweeps=n, layout=lay)
+            for i, (L, lay, x, w, n) in enumerate(specs)]
+    say("case batch edge set", [(j.L, j.layout, j.composition, j.sweeps) for j in jobs])
+    b = kk.Batch(jobs)
+    b.run()
+    for i, j in enumerate(jobs):
+        ref = oracle.init(j.L, j.composition, j.seed)
+        acc = oracle.sweeps(ref, j.omega, j.seed, 0, j.sweeps)
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), ref), (i, j.L)
+        assert s.stats() == (j.sweeps, j.sweeps * j.L * j.L, acc), (i, j.L)
+        assert s.energy()[0] == oracle.energy(ref)
     b.close()
