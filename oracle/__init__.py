@@ -62,6 +62,7 @@ def _load():
         "ko_init": (ctypes.c_int, [u8p, U32, D, U64]),
         "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
         "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
+        "ko_similar_sampled": (U64, [u8p, U32, U64, U64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -177,6 +178,41 @@ def cluster_hist(s: np.ndarray, species: int = 1):
     c = cluster_counts(s, species)
     nz = np.nonzero(c)[0]
     return [(int(k), int(c[k])) for k in nz]
+
+
+def similar_sampled(s: np.ndarray, seed: int, t: int) -> int:
+    """Count of sites whose randomly drawn neighbour is of the same type
+    (the random-neighbour estimate of the similar first-neighbour fraction is
+    this count over the number of sites)."""
+    s = _lattice(s)
+    return int(_load().ko_similar_sampled(_ptr(s, ctypes.c_uint8), s.shape[0], seed, t))
+
+
+def observables(s: np.ndarray, omega: float, species: int, seed: int, t: int) -> dict:
+    """The observables of one lattice state, from their definitions:
+    N_AB and E/kT = omega * N_AB; the exact similar first-neighbour fraction
+    1 - N_AB / (2N) (each of the 2N bonds joins like or unlike sites) and its
+    random-neighbour estimate; the number of clusters of `species`, the
+    number-average size sum s h(s) / sum h(s), the weight-average size
+    sum s^2 h(s) / sum s h(s) and the largest size.  Sums are exact integers;
+    each ratio is one correctly rounded division."""
+    s = _lattice(s)
+    N = s.shape[0] * s.shape[0]
+    nab = energy(s)
+    c = cluster_counts(s, species)
+    sizes = np.nonzero(c)[0]
+    n_cl = int(sum(int(c[k]) for k in sizes))
+    s1 = int(sum(int(k) * int(c[k]) for k in sizes))
+    s2 = int(sum(int(k) * int(k) * int(c[k]) for k in sizes))
+    return {
+        "n_unlike": nab, "energy_kT": omega * nab,
+        "similar_exact": 1.0 - nab / (2 * N),
+        "similar_sampled": similar_sampled(s, seed, t) / N,
+        "n_clusters": n_cl,
+        "size_number_avg": s1 / n_cl if n_cl else 0.0,
+        "size_weight_avg": s2 / s1 if s1 else 0.0,
+        "size_max": int(sizes.max()) if len(sizes) else 0,
+    }
 
 
 def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:

@@ -45,6 +45,7 @@
 #define KO_TAG_EXT 2u
 #define KO_TAG_ORDER 3u
 #define KO_TAG_INIT 4u
+#define KO_TAG_OBSERVE 5u
 
 /* ---------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
@@ -364,6 +365,38 @@ uint64_t ko_energy(const uint8_t *s, uint32_t L)
             nab += (v != s[(size_t)wrap_add(y, +1, L) * L + x]);
         }
     return nab;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Random-neighbour estimate of the fraction of similar first neighbours     */
+/* (Materials and Methods, "Image analysis": the classical approach draws,   */
+/* for every site, one of its nearest neighbours at random and counts the    */
+/* pairs of equal type; the estimate is that count over the lattice size).   */
+/* The draw of site (x, y) taken at sweep counter t is the top two bits of   */
+/* word (x mod 4) of Philox block (y, x div 4, t_lo, t_hi28 | TAG_OBSERVE<<28)*/
+/* with 0 = +x, 1 = -x, 2 = +y, 3 = -y.  Returns the count.                  */
+/* ---------------------------------------------------------------------- */
+uint64_t ko_similar_sampled(const uint8_t *s, uint32_t L, uint64_t seed, uint64_t t)
+{
+    uint32_t key[2], ctr[4], w[4];
+    uint64_t same = 0;
+    uint32_t x, y;
+    seed_to_key(seed, key);
+    for (y = 0; y < L; ++y)
+        for (x = 0; x < L; ++x) {
+            uint32_t dir, nx, ny;
+            if ((x & 3u) == 0) {
+                ctr[0] = y;
+                ctr[1] = x >> 2;
+                ctr[2] = (uint32_t)t;
+                ctr[3] = ctr3(t, KO_TAG_OBSERVE);
+                ko_philox4x32_10(ctr, key, w);
+            }
+            dir = w[x & 3u] >> 30;
+            partner_of(x, y, dir, L, &nx, &ny);
+            same += (s[(size_t)y * L + x] == s[(size_t)ny * L + nx]);
+        }
+    return same;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -444,3 +444,50 @@ def test_cluster_hist_special_cases(orc):
     s = np.zeros((L, L), np.uint8)
     s[0, 0] = s[0, L - 1] = s[L - 1, 0] = s[L - 1, L - 1] = 1
     assert orc.cluster_hist(s, 1) == [(4, 1)]
+
+
+# ---------------------------------------------------------------------------
+# Random-neighbour estimate of the similar first-neighbour fraction
+# ---------------------------------------------------------------------------
+def test_similar_sampled_special_lattices(orc):
+    L = 32
+    N = L * L
+    for v in (0, 1):
+        assert orc.similar_sampled(np.full((L, L), v, np.uint8), 7, 3) == N
+    cb = (np.indices((L, L)).sum(0) % 2).astype(np.uint8)
+    assert orc.similar_sampled(cb, 7, 3) == 0   # every neighbour differs
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_similar_sampled_stripes_pick_each_axis_half_the_time(orc, axis):
+    # rows (or columns) alternate: only the draws along the stripes match
+    L = 64
+    N = L * L
+    st = (np.indices((L, L))[axis] % 2).astype(np.uint8)
+    fr = np.array([orc.similar_sampled(st, 11, t) for t in range(40)]) / N
+    assert abs(fr.mean() - 0.5) < 5 * math.sqrt(0.25 / (N * len(fr)))
+
+
+def test_similar_sampled_is_unbiased_for_the_exact_fraction(orc):
+    # E[count / N] = (1/N) sum_i (like neighbours of i) / 4 = 1 - N_AB / (2N)
+    L = 48
+    N = L * L
+    for x, seed in ((0.5, 1), (0.3, 2)):
+        s = orc.init(L, x, seed)
+        exact = 1.0 - orc.energy(s) / (2 * N)
+        fr = np.array([orc.similar_sampled(s, 99, t) for t in range(300)]) / N
+        assert abs(fr.mean() - exact) < 5 * fr.std(ddof=1) / math.sqrt(len(fr)) + 1e-12
+        assert len(set(fr)) > 10   # a fresh draw at every t
+
+
+def test_observables_of_a_known_state(orc):
+    # two 2x2 blocks of species 1 on an 8x8 torus: 8 unlike bonds each
+    s = np.zeros((8, 8), np.uint8)
+    s[1:3, 1:3] = 1
+    s[5:7, 4:6] = 1
+    o = orc.observables(s, 0.5, 1, 3, 0)
+    assert o["n_unlike"] == 16 and o["energy_kT"] == 8.0
+    assert o["similar_exact"] == 1.0 - 16 / 128
+    assert (o["n_clusters"], o["size_number_avg"], o["size_weight_avg"], o["size_max"]) == (2, 4.0, 4.0, 4)
+    o0 = orc.observables(s, 0.5, 0, 3, 0)
+    assert (o0["n_clusters"], o0["size_max"]) == (1, 56)
