@@ -102,6 +102,32 @@ kk_status kk_energy(kk_sim *h, uint64_t *n_unlike, double *energy_kT);
  * small; `out` may be NULL when cap == 0. */
 kk_status kk_cluster_hist(kk_sim *h, int species, kk_hist_entry *out, size_t cap, size_t *n_out);
 
+/* Observables of the current lattice (Results, "Cluster Analysis": average
+ * cluster size over time; Materials and Methods, "Image analysis": the
+ * fraction of similar first neighbours).  Every ratio is one correctly
+ * rounded division of exact integer sums. */
+typedef struct {
+    uint64_t sweep;            /* sweep counter t when taken */
+    uint64_t n_unlike;         /* N_AB */
+    double energy_kT;          /* omega * N_AB */
+    double similar_exact;      /* 1 - N_AB / (2N): the fraction of the 2N bonds joining like sites */
+    double similar_sampled;    /* random-neighbour estimate: every site draws one of its 4
+                                  neighbours (top two bits of its word of Philox block
+                                  (y, x / 4, t, tag 5): +x, -x, +y, -y); the fraction of draws
+                                  that match its type */
+    uint64_t n_clusters;       /* clusters of `species` (as kk_cluster_hist) */
+    double size_number_avg;    /* sum s h(s) / sum h(s); 0 without clusters */
+    double size_weight_avg;    /* sum s^2 h(s) / sum s h(s); 0 without clusters */
+    uint64_t size_max;         /* largest cluster; 0 without clusters */
+} kk_observables;
+
+/* Take the observables of the current lattice for `species` (0 or 1). */
+kk_status kk_observe(kk_sim *h, int species, kk_observables *out);
+
+/* A time series: count times, run `every` sweeps (every >= 1) and take the
+ * observables; out must hold count records. */
+kk_status kk_sweep_series(kk_sim *h, uint64_t every, uint64_t count, int species, kk_observables *out);
+
 /* Copy the lattice to host_out (n must be L*L bytes, values 0/1). */
 kk_status kk_get_lattice(kk_sim *h, uint8_t *host_out, size_t n);
 
@@ -187,7 +213,7 @@ kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
 /* Autotune the tiles of the tiled replicas: time whole batch runs of
  * trial_sweeps sweeps (0 = 10) for tiles (words x at most rows) of
- * 8 x 128, 16 x 84, 8 x 64 and 16 x 42 (smaller tiles give more
+ * 8 x 128, 16 x 84, 8 x 64, 16 x 42, 8 x 32 and 8 x 16 (smaller tiles give more
  * workgroups when the batch holds little work, larger ones less halo work),
  * keep the fastest and re-plan.
  * Every replica's lattice, sweep counter and counters are restored exactly

@@ -554,6 +554,52 @@ kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap
   return KK_OK;
 }
 
+kk_status kk_observe(kk_sim* h, int species, kk_observables* out) {
+  KK_GUARD(h);
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  if (species != 0 && species != 1) return set_error(KK_EINVAL, "species must be 0 or 1");
+  kk_observables o{};
+  o.sweep = h->t;
+  kk_status st = kk_energy(h, &o.n_unlike, &o.energy_kT);
+  if (st != KK_OK) return st;
+  const uint64_t N = (uint64_t)h->L * (uint64_t)h->L;
+  o.similar_exact = 1.0 - (double)o.n_unlike / (double)(2 * N);
+  KK_HIP(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
+  KK_HIP(launch_similar_sampled(h->lat[h->cur], h->layout, h->L, h->k0, h->k1, h->t, h->counters, h->stream));
+  unsigned long long same = 0;
+  KK_HIP(hipMemcpyAsync(&same, h->counters, sizeof same, hipMemcpyDeviceToHost, h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  o.similar_sampled = (double)same / (double)N;
+  size_t n = 0;
+  st = kk_cluster_hist(h, species, nullptr, 0, &n);
+  if (st != KK_OK && st != KK_ETRUNC) return st;
+  uint64_t nc = 0, s1 = 0, s2 = 0, smax = 0;
+  for (const kk_hist_entry& e : h->hist_cache) {  // filled by the call above
+    nc += e.count;
+    s1 += e.size * e.count;
+    s2 += e.size * e.size * e.count;
+    smax = std::max(smax, e.size);
+  }
+  o.n_clusters = nc;
+  o.size_number_avg = nc ? (double)s1 / (double)nc : 0.0;
+  o.size_weight_avg = s1 ? (double)s2 / (double)s1 : 0.0;
+  o.size_max = smax;
+  *out = o;
+  return KK_OK;
+}
+
+kk_status kk_sweep_series(kk_sim* h, uint64_t every, uint64_t count, int species, kk_observables* out) {
+  KK_GUARD(h);
+  if (every == 0) return set_error(KK_EINVAL, "every must be at least 1");
+  if (count > 0 && !out) return set_error(KK_EINVAL, "out is NULL");
+  for (uint64_t i = 0; i < count; ++i) {
+    kk_status st = kk_sweep(h, every);
+    if (st == KK_OK) st = kk_observe(h, species, &out[i]);
+    if (st != KK_OK) return st;
+  }
+  return KK_OK;
+}
+
 kk_status kk_get_lattice(kk_sim* h, uint8_t* host_out, size_t n) {
   KK_GUARD(h);
   const size_t N = (size_t)h->L * h->L;

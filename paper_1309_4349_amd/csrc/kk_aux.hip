@@ -48,6 +48,36 @@ __global__ __launch_bounds__(256) void energy_int8(const uint8_t* lat, int L, un
   if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
+// Random-neighbour estimate of the similar first-neighbour fraction: every
+// site draws one of its 4 neighbours (top two bits of its word of Philox block
+// (y, x / 4, t, tag 5): +x, -x, +y, -y) and counts when both are of the same
+// type.  One thread per 4-site group (one Philox block); L % 4 == 0.
+__global__ __launch_bounds__(256) void similar_sampled(const void* lat, int layout, int L, uint32_t k0, uint32_t k1,
+                                                       uint64_t t, unsigned long long* out) {
+  const int g4 = L >> 2;
+  const size_t n = (size_t)L * g4;
+  const uint32_t tl = (uint32_t)t, th = ctr_hi(t, kTagObserve);
+  unsigned long long acc = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / g4), q = (int)(i - (size_t)y * g4);
+    const Philox4 r = philox10((uint32_t)y, (uint32_t)q, tl, th, k0, k1);
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int x = 4 * q + m;
+      const uint32_t dir = w[m] >> 30;
+      int nx = x, ny = y;
+      if (dir == 0u) nx = (x + 1 == L) ? 0 : x + 1;
+      else if (dir == 1u) nx = (x == 0) ? L - 1 : x - 1;
+      else if (dir == 2u) ny = (y + 1 == L) ? 0 : y + 1;
+      else ny = (y == 0) ? L - 1 : y - 1;
+      acc += (site_bit(lat, layout, L, x, y) == site_bit(lat, layout, L, nx, ny));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
 // ---------------------------------------------------------------------------
 // Initial placement: each site's 64-bit key is Philox block (y, x, 0, tag 4)
 // words 0 and 1; the n1 sites with the smallest (key, index) get type 1.
@@ -267,6 +297,13 @@ hipError_t launch_energy(const void* lat, int layout, int L, unsigned long long*
   else
     hipLaunchKernelGGL(energy_int8, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream,
                        static_cast<const uint8_t*>(lat), L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_similar_sampled(const void* lat, int layout, int L, uint32_t k0, uint32_t k1, uint64_t t,
+                                 unsigned long long* out, hipStream_t stream) {
+  hipLaunchKernelGGL(similar_sampled, dim3(grid_for((size_t)L * (L >> 2), 256)), dim3(256), 0, stream, lat, layout, L,
+                     k0, k1, t, out);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ constexpr uint32_t kTagSweep = 1u;  // per-sweep bit-sliced random planes
 constexpr uint32_t kTagExt = 2u;    // low 32 bits of a 42-bit uniform (ties only)
 constexpr uint32_t kTagOrder = 3u;  // per-sweep class order
 constexpr uint32_t kTagInit = 4u;   // initial-placement sort keys
+constexpr uint32_t kTagObserve = 5u;  // random-neighbour draws of the observables
 
 constexpr int kPlanes = 12;  // 2 direction planes + 10 uniform-prefix planes
 

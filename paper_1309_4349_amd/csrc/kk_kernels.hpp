@@ -67,6 +67,10 @@ size_t batch_resident_lds_bytes(int L);
 // N_AB (unlike nearest-neighbour bonds) added into *out.
 hipError_t launch_energy(const void* lat, int layout, int L, unsigned long long* out, hipStream_t stream);
 
+// Count of sites whose randomly drawn neighbour has the same type, added into *out.
+hipError_t launch_similar_sampled(const void* lat, int layout, int L, uint32_t k0, uint32_t k1, uint64_t t,
+                                 unsigned long long* out, hipStream_t stream);
+
 // Initial placement.
 hipError_t launch_init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1, hipStream_t stream);
 hipError_t launch_radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, int shift, unsigned* hist256,

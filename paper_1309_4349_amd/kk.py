@@ -21,7 +21,7 @@ _LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPAC
 
 EXPORTS = [
     "kk_create", "kk_create_ex", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
-    "kk_get_lattice", "kk_set_lattice", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
+    "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
@@ -38,6 +38,16 @@ class KKError(RuntimeError):
 
 class HistEntry(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint64), ("count", ctypes.c_uint64)]
+
+
+class Observables(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_uint64), ("n_unlike", ctypes.c_uint64), ("energy_kT", ctypes.c_double),
+                ("similar_exact", ctypes.c_double), ("similar_sampled", ctypes.c_double),
+                ("n_clusters", ctypes.c_uint64), ("size_number_avg", ctypes.c_double),
+                ("size_weight_avg", ctypes.c_double), ("size_max", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Replica(ctypes.Structure):
@@ -98,6 +108,8 @@ def load(path: str = LIB_PATH):
         "kk_energy": [P, u64p, dp],
         "kk_cluster_hist": [P, I, ctypes.POINTER(HistEntry), ctypes.c_size_t, szp],
         "kk_get_lattice": [P, P, ctypes.c_size_t],
+        "kk_observe": [P, I, ctypes.POINTER(Observables)],
+        "kk_sweep_series": [P, U64, U64, I, ctypes.POINTER(Observables)],
         "kk_set_lattice": [P, P, ctypes.c_size_t, U64],
         "kk_stats": [P, u64p, u64p, u64p],
         "kk_thresholds": [P, u64p],
@@ -205,6 +217,16 @@ class Sim:
         buf = (HistEntry * max(1, need.value))()
         _check(lib.kk_cluster_hist(self._h, species, buf, need.value, ctypes.byref(need)))
         return [(int(buf[i].size), int(buf[i].count)) for i in range(need.value)]
+
+    def observe(self, species: int = 1) -> dict:
+        o = Observables()
+        _check(load().kk_observe(self._h, species, ctypes.byref(o)))
+        return o.as_dict()
+
+    def series(self, every: int, count: int, species: int = 1) -> List[dict]:
+        buf = (Observables * max(1, count))()
+        _check(load().kk_sweep_series(self._h, every, count, species, buf))
+        return [buf[i].as_dict() for i in range(count)]
 
     def get_lattice(self) -> np.ndarray:
         out = np.empty((self.L, self.L), dtype=np.uint8)
