@@ -300,6 +300,13 @@ def main():
                 "hbm_frac": round(hbm / HBM_PEAK_GBS, 5),
                 "tile": {"words": tw, "rows": th, "units_per_thread": ku}}
     log(f"[bench] sweep kernel {per_launch_s * 1e6:.2f} us/launch, {ops:.0f} Gop/s, {hbm:.1f} GB/s algorithmic")
+    # observables of the final state (labelling, N_AB and the random-neighbour draw)
+    sim.sweep(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs = sim.observe(1)
+    observe_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] observables in {observe_ms:.2f} ms: {obs}")
     sim.close()
 
     batched = None
@@ -329,6 +336,9 @@ def main():
                    "L": job.L, "composition": job.composition, "omega": job.omega,
                    "sweeps_per_step": job.sweeps, "layout": "bitpacked"},
         "roofline": roofline,
+        "observables": {"ms": observe_ms, "similar_exact": obs["similar_exact"],
+                        "similar_sampled": obs["similar_sampled"], "size_number_avg": obs["size_number_avg"],
+                        "size_weight_avg": obs["size_weight_avg"]},
         "cpu_baseline": cpu,
     }
     if batched is not None:
