@@ -63,6 +63,14 @@ def _load():
         "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
         "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
         "ko_similar_sampled": (U64, [u8p, U32, U64, U64]),
+        "ko_tri_thresholds": (None, [D, u64p]),
+        "ko_tri_phase_order": (None, [U64, U64, c_int_p]),
+        "ko_tri_site_randoms": (None, [U64, U64, U64, u32p, u32p]),
+        "ko_tri_local_dnab": (ctypes.c_int, [u8p, U32, U64, U32]),
+        "ko_tri_sweeps": (U64, [u8p, U32, D, U64, U64, U64]),
+        "ko_tri_energy": (U64, [u8p, U32]),
+        "ko_tri_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
+        "ko_tri_similar_sampled": (U64, [u8p, U32, U64, U64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -213,6 +221,64 @@ def observables(s: np.ndarray, omega: float, species: int, seed: int, t: int) ->
         "size_weight_avg": s2 / s1 if s1 else 0.0,
         "size_max": int(sizes.max()) if len(sizes) else 0,
     }
+
+
+# --------------------------------------------------------------------------
+# Triangular lattice, helical boundaries (sites i = y*L + x on one ring,
+# neighbours i +- 1, i +- L, i +- (L - 1) mod N); L % 8 == 4.
+# --------------------------------------------------------------------------
+def tri_thresholds(omega: float) -> np.ndarray:
+    T = np.zeros(11, dtype=np.uint64)
+    _load().ko_tri_thresholds(float(omega), _ptr(T, ctypes.c_uint64))
+    return T
+
+
+def tri_phase_order(seed: int, t: int) -> list:
+    p = (ctypes.c_int * 16)()
+    _load().ko_tri_phase_order(seed, t, p)
+    return list(p)
+
+
+def tri_site_randoms(seed: int, t: int, i: int):
+    d, u = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().ko_tri_site_randoms(seed, t, i, ctypes.byref(d), ctypes.byref(u))
+    return d.value, u.value
+
+
+def tri_local_dnab(s: np.ndarray, i: int, direction: int) -> int:
+    s = _lattice(s)
+    return int(_load().ko_tri_local_dnab(_ptr(s, ctypes.c_uint8), s.shape[0], i, direction))
+
+
+def tri_sweeps(s: np.ndarray, omega: float, seed: int, t0: int, n: int) -> int:
+    s = _lattice(s)
+    return int(_load().ko_tri_sweeps(_ptr(s, ctypes.c_uint8), s.shape[0], float(omega), seed, t0, n))
+
+
+def tri_energy(s: np.ndarray) -> int:
+    s = _lattice(s)
+    return int(_load().ko_tri_energy(_ptr(s, ctypes.c_uint8), s.shape[0]))
+
+
+def tri_cluster_counts(s: np.ndarray, species: int = 1) -> np.ndarray:
+    s = _lattice(s)
+    L = s.shape[0]
+    counts = np.zeros(L * L + 1, dtype=np.uint64)
+    r = _load().ko_tri_cluster_counts(_ptr(s, ctypes.c_uint8), L, int(species), _ptr(counts, ctypes.c_uint64))
+    if r == 2**64 - 1:
+        raise MemoryError("oracle cluster allocation failed")
+    return counts
+
+
+def tri_cluster_hist(s: np.ndarray, species: int = 1):
+    c = tri_cluster_counts(s, species)
+    nz = np.nonzero(c)[0]
+    return [(int(k), int(c[k])) for k in nz]
+
+
+def tri_similar_sampled(s: np.ndarray, seed: int, t: int) -> int:
+    s = _lattice(s)
+    return int(_load().ko_tri_similar_sampled(_ptr(s, ctypes.c_uint8), s.shape[0], seed, t))
 
 
 def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:

@@ -602,3 +602,218 @@ uint64_t ko_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_seed
     }
     return accepted;
 }
+
+/* ====================================================================== */
+/* Triangular lattice with helical boundary conditions (the paper's own    */
+/* model: Materials and Methods, "Monte Carlo model with Kawasaki based    */
+/* kinetics", Fig. 2, and "Cluster Analysis methods": six neighbours under */
+/* helical boundaries).                                                    */
+/*                                                                         */
+/* Sites i = y*L + x, 0 <= i < N = L*L, form one ring: the neighbours of i */
+/* are i +- 1, i +- L and i +- (L - 1) modulo N (the last site of a row is */
+/* followed by the first of the next).  Schedule: class(i) = i mod 16;     */
+/* for L = 4 (mod 8) two sites of one class are at least 4 steps apart, so */
+/* no exchange of a class reads a site another one writes.  A sweep visits */
+/* the 16 classes in a random order.                                       */
+/* Random numbers (Philox4x32-10, key = seed):                             */
+/*   site i at sweep t: block (i div 2, 0, t_lo, t_hi28 | 6<<28), words     */
+/*   2(i mod 2) (direction) and 2(i mod 2) + 1 (uniform U);                 */
+/*   direction d = (word * 6) >> 32 picks offset +1, -1, +L, -L, +(L-1),   */
+/*   -(L-1) for d = 0..5;                                                   */
+/*   phase order: blocks (j, 0, t_lo, t_hi28 | 7<<28), j = 0..3 give       */
+/*   w[0..15]; for i = 15..1 swap perm[i] with perm[(w[15-i]*(i+1)) >> 32]. */
+/* Attempt: n = unlike neighbours of the centre other than the partner +   */
+/* unlike neighbours of the partner other than the centre (0..10); dN_AB =  */
+/* 10 - 2n; accept iff U < T[n] = min(2^32, ceil(exp(-omega(10-2n)) 2^32)). */
+/* ====================================================================== */
+#define KO_TAG_TRI 6u
+#define KO_TAG_TRI_ORDER 7u
+
+static int64_t tri_offset(uint32_t L, uint32_t d)
+{
+    static const int sign[6] = {+1, -1, +1, -1, +1, -1};
+    int64_t mag = (d < 2) ? 1 : (d < 4) ? (int64_t)L : (int64_t)L - 1;
+    return sign[d] * mag;
+}
+
+static uint64_t tri_nb(uint64_t i, int64_t off, uint64_t N)
+{
+    int64_t j = (int64_t)i + off;
+    j %= (int64_t)N;
+    if (j < 0) j += (int64_t)N;
+    return (uint64_t)j;
+}
+
+void ko_tri_thresholds(double omega, uint64_t T[11])
+{
+    int n;
+    for (n = 0; n <= 10; ++n) {
+        double p = exp(-omega * (double)(10 - 2 * n));
+        double v = ceil(p * 4294967296.0);
+        T[n] = (v >= 4294967296.0) ? 4294967296ull : (uint64_t)v;
+    }
+}
+
+void ko_tri_phase_order(uint64_t seed, uint64_t t, int perm[16])
+{
+    uint32_t key[2], ctr[4], w[16], b[4];
+    int i, j;
+    seed_to_key(seed, key);
+    for (j = 0; j < 4; ++j) {
+        ctr[0] = (uint32_t)j;
+        ctr[1] = 0u;
+        ctr[2] = (uint32_t)t;
+        ctr[3] = ctr3(t, KO_TAG_TRI_ORDER);
+        ko_philox4x32_10(ctr, key, b);
+        w[4 * j] = b[0];
+        w[4 * j + 1] = b[1];
+        w[4 * j + 2] = b[2];
+        w[4 * j + 3] = b[3];
+    }
+    for (i = 0; i < 16; ++i) perm[i] = i;
+    for (i = 15; i >= 1; --i) {
+        int k = (int)(((uint64_t)w[15 - i] * (uint64_t)(i + 1)) >> 32);
+        int tmp = perm[i];
+        perm[i] = perm[k];
+        perm[k] = tmp;
+    }
+}
+
+/* Direction (0..5) and uniform of site i at sweep t. */
+void ko_tri_site_randoms(uint64_t seed, uint64_t t, uint64_t i, uint32_t *dir, uint32_t *u)
+{
+    uint32_t key[2], ctr[4], b[4];
+    seed_to_key(seed, key);
+    ctr[0] = (uint32_t)(i >> 1);
+    ctr[1] = 0u;
+    ctr[2] = (uint32_t)t;
+    ctr[3] = ctr3(t, KO_TAG_TRI);
+    ko_philox4x32_10(ctr, key, b);
+    *dir = (uint32_t)(((uint64_t)b[2 * (i & 1u)] * 6u) >> 32);
+    *u = b[2 * (i & 1u) + 1];
+}
+
+static int tri_unlike_except(const uint8_t *s, uint32_t L, uint64_t i, uint64_t other)
+{
+    uint64_t N = (uint64_t)L * L;
+    uint32_t d;
+    int n = 0;
+    for (d = 0; d < 6; ++d) {
+        uint64_t j = tri_nb(i, tri_offset(L, d), N);
+        if (j != other) n += (s[j] != s[i]);
+    }
+    return n;
+}
+
+/* dN_AB of exchanging site i with its neighbour in direction d (0 when alike). */
+int ko_tri_local_dnab(const uint8_t *s, uint32_t L, uint64_t i, uint32_t d)
+{
+    uint64_t N = (uint64_t)L * L;
+    uint64_t b = tri_nb(i, tri_offset(L, d), N);
+    if (s[i] == s[b]) return 0;
+    return 10 - 2 * (tri_unlike_except(s, L, i, b) + tri_unlike_except(s, L, b, i));
+}
+
+uint64_t ko_tri_sweeps(uint8_t *s, uint32_t L, double omega, uint64_t seed, uint64_t t0, uint64_t n_sweeps)
+{
+    uint64_t T[11], N = (uint64_t)L * L, acc = 0, t;
+    int perm[16], p;
+    ko_tri_thresholds(omega, T);
+    for (t = t0; t < t0 + n_sweeps; ++t) {
+        ko_tri_phase_order(seed, t, perm);
+        for (p = 0; p < 16; ++p) {
+            int64_t i;
+            uint64_t phase_acc = 0;
+            /* centres of one class never interact: any order gives the same result */
+#pragma omp parallel for reduction(+ : phase_acc) schedule(static)
+            for (i = perm[p]; i < (int64_t)N; i += 16) {
+                uint32_t d, u;
+                uint64_t b;
+                ko_tri_site_randoms(seed, t, (uint64_t)i, &d, &u);
+                b = tri_nb((uint64_t)i, tri_offset(L, d), N);
+                if (s[i] != s[b]) {
+                    int n = tri_unlike_except(s, L, (uint64_t)i, b) + tri_unlike_except(s, L, b, (uint64_t)i);
+                    if ((uint64_t)u < T[n]) {
+                        uint8_t tmp = s[i];
+                        s[i] = s[b];
+                        s[b] = tmp;
+                        ++phase_acc;
+                    }
+                }
+            }
+            acc += phase_acc;
+        }
+    }
+    return acc;
+}
+
+/* N_AB over the 3N bonds (i, i+1), (i, i+L), (i, i+L-1). */
+uint64_t ko_tri_energy(const uint8_t *s, uint32_t L)
+{
+    uint64_t N = (uint64_t)L * L, i, nab = 0;
+    for (i = 0; i < N; ++i) {
+        nab += (s[i] != s[tri_nb(i, 1, N)]);
+        nab += (s[i] != s[tri_nb(i, (int64_t)L, N)]);
+        nab += (s[i] != s[tri_nb(i, (int64_t)L - 1, N)]);
+    }
+    return nab;
+}
+
+/* Cluster counts of one species, six neighbours, helical boundaries (BFS). */
+uint64_t ko_tri_cluster_counts(const uint8_t *s, uint32_t L, int species, uint64_t *counts)
+{
+    uint64_t N = (uint64_t)L * L, i, nclusters = 0;
+    uint8_t *seen = (uint8_t *)calloc(N, 1);
+    uint64_t *queue = (uint64_t *)malloc(N * sizeof(uint64_t));
+    if (!seen || !queue) {
+        free(seen);
+        free(queue);
+        return ~(uint64_t)0;
+    }
+    for (i = 0; i <= N; ++i) counts[i] = 0;
+    for (i = 0; i < N; ++i) {
+        uint64_t head = 0, tail = 0;
+        if (s[i] != species || seen[i]) continue;
+        seen[i] = 1;
+        queue[tail++] = i;
+        while (head < tail) {
+            uint64_t c = queue[head++];
+            uint32_t d;
+            for (d = 0; d < 6; ++d) {
+                uint64_t j = tri_nb(c, tri_offset(L, d), N);
+                if (s[j] == species && !seen[j]) {
+                    seen[j] = 1;
+                    queue[tail++] = j;
+                }
+            }
+        }
+        counts[tail] += 1;
+        ++nclusters;
+    }
+    free(seen);
+    free(queue);
+    return nclusters;
+}
+
+/* Random-neighbour similar count on the triangular lattice: site i draws   */
+/* d = (word * 6) >> 32 from word (i mod 4) of Philox block                 */
+/* (i div 4, 1, t_lo, t_hi28 | TAG_OBSERVE<<28).                             */
+uint64_t ko_tri_similar_sampled(const uint8_t *s, uint32_t L, uint64_t seed, uint64_t t)
+{
+    uint32_t key[2], ctr[4], w[4];
+    uint64_t N = (uint64_t)L * L, i, same = 0;
+    seed_to_key(seed, key);
+    for (i = 0; i < N; ++i) {
+        uint32_t d;
+        if ((i & 3u) == 0) {
+            ctr[0] = (uint32_t)(i >> 2);
+            ctr[1] = 1u;
+            ctr[2] = (uint32_t)t;
+            ctr[3] = ctr3(t, KO_TAG_OBSERVE);
+            ko_philox4x32_10(ctr, key, w);
+        }
+        d = (uint32_t)(((uint64_t)w[i & 3u] * 6u) >> 32);
+        same += (s[i] == s[tri_nb(i, tri_offset(L, d), N)]);
+    }
+    return same;
+}
