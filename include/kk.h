@@ -80,6 +80,38 @@ kk_status kk_create(kk_sim **out, uint32_t L, double composition, double omega_k
 kk_status kk_create_ex(kk_sim **out, uint32_t L, double composition, double omega_kT, uint64_t seed,
                        uint32_t layout, void *hip_stream);
 
+/* Create a simulation on the paper's own lattice (Materials and Methods, Fig. 2
+ * and "Cluster Analysis methods"): triangular, six neighbours, helical
+ * boundaries.  Sites i = y*L + x (0 <= i < N = L*L) form one ring; the
+ * neighbours of i are i +- 1, i +- L and i +- (L-1) mod N, so N_AB counts the
+ * 3N bonds (i, i+1), (i, i+L), (i, i+L-1).  L must satisfy L % 8 == 4,
+ * 4 <= L <= 32764; the lattice is stored one byte per site (KK_LAYOUT_INT8) and
+ * initialised exactly as kk_create's random start.  A sweep is N attempts in 16
+ * conflict-free classes (class(i) = i mod 16), run in a random order:
+ *   class order of sweep t: Philox words of blocks (j, 0, t_lo, t_hi28 | 7<<28),
+ *     j = 0..3, w[0..15]; Fisher-Yates from the identity, step k = 15..1 swaps
+ *     entries k and (w[15-k] * (k+1)) >> 32;
+ *   site i at sweep t: block (i/2, 0, t_lo, t_hi28 | 6<<28); word 2(i%2) picks
+ *     the partner direction d = (w * 6) >> 32 (offsets +1, -1, +L, -L, +(L-1),
+ *     -(L-1)), word 2(i%2)+1 is the uniform U;
+ *   unlike pair (i, b) with n unlike neighbours (each excluding the other,
+ *     0..10): exchange iff U < T[n] = min(2^32, ceil(exp(-omega (10-2n)) 2^32)).
+ * kk_sweep, kk_sweep_async, kk_sweep_timed (16 launches per sweep), kk_energy,
+ * kk_cluster_hist (six-connected clusters), kk_observe and kk_sweep_series
+ * (similar_exact = 1 - N_AB/(3N); similar_sampled draws one of the six
+ * neighbours with d = (w*6)>>32 from word i%4 of block (i/4, 1, t_lo,
+ * t_hi28 | 5<<28)), kk_get_lattice, kk_set_lattice, kk_stats, kk_info and
+ * kk_stream work on it; kk_thresholds, kk_set_tile, kk_get_tile and
+ * kk_autotune return KK_EINVAL. */
+kk_status kk_create_triangular(kk_sim **out, uint32_t L, double composition, double omega_kT, uint64_t seed,
+                               void *hip_stream);
+
+/* The 11 thresholds T[0..10] of a triangular handle (KK_EINVAL on a square one). */
+kk_status kk_tri_thresholds(kk_sim *h, uint64_t out[11]);
+
+/* 0 for the square torus, 1 for the triangular helical lattice. */
+kk_status kk_geometry(kk_sim *h, uint32_t *geometry);
+
 /* Run n_sweeps sweeps (N attempts each, the paper's MPKK step), t .. t+n-1,
  * and wait for them.  Advances the sweep counter. */
 kk_status kk_sweep(kk_sim *h, uint64_t n_sweeps);

@@ -206,16 +206,18 @@ def observables(s: np.ndarray, omega: float, species: int, seed: int, t: int) ->
     each ratio is one correctly rounded division."""
     s = _lattice(s)
     N = s.shape[0] * s.shape[0]
-    nab = energy(s)
-    c = cluster_counts(s, species)
+    return _observables_of(energy(s), 2 * N, cluster_counts(s, species), similar_sampled(s, seed, t), N, omega)
+
+
+def _observables_of(nab: int, bonds: int, c: np.ndarray, same: int, N: int, omega: float) -> dict:
     sizes = np.nonzero(c)[0]
     n_cl = int(sum(int(c[k]) for k in sizes))
     s1 = int(sum(int(k) * int(c[k]) for k in sizes))
     s2 = int(sum(int(k) * int(k) * int(c[k]) for k in sizes))
     return {
         "n_unlike": nab, "energy_kT": omega * nab,
-        "similar_exact": 1.0 - nab / (2 * N),
-        "similar_sampled": similar_sampled(s, seed, t) / N,
+        "similar_exact": 1.0 - nab / bonds,
+        "similar_sampled": same / N,
         "n_clusters": n_cl,
         "size_number_avg": s1 / n_cl if n_cl else 0.0,
         "size_weight_avg": s2 / s1 if s1 else 0.0,
@@ -279,6 +281,15 @@ def tri_cluster_hist(s: np.ndarray, species: int = 1):
 def tri_similar_sampled(s: np.ndarray, seed: int, t: int) -> int:
     s = _lattice(s)
     return int(_load().ko_tri_similar_sampled(_ptr(s, ctypes.c_uint8), s.shape[0], seed, t))
+
+
+def tri_observables(s: np.ndarray, omega: float, species: int, seed: int, t: int) -> dict:
+    """observables() on the triangular lattice: 3N bonds, six-connected
+    clusters, the six-neighbour random draw."""
+    s = _lattice(s)
+    N = s.shape[0] * s.shape[0]
+    return _observables_of(tri_energy(s), 3 * N, tri_cluster_counts(s, species), tri_similar_sampled(s, seed, t),
+                           N, omega)
 
 
 def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:

@@ -314,7 +314,7 @@ kk_status reset_partials(kk_sim* h) {
     (void)hipFree(h->partials);
     h->partials = nullptr;
   }
-  h->npartials = tile_count(h->L, h->tile);
+  h->npartials = h->geom ? (size_t)kTriPartials : tile_count(h->L, h->tile);
   kk_status st = dmalloc(h, (void**)&h->partials, h->npartials * sizeof(unsigned long long));
   if (st != KK_OK) return st;
   KK_HIP(hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream));
@@ -325,6 +325,34 @@ kk_status reset_partials(kk_sim* h) {
 // Launch sweeps [h->t, h->t + n) on the handle's stream.  With `timing`, an
 // event pair brackets every launch and the kernel time is accumulated.
 kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
+  if (h->geom == 1) {
+    // triangular: 16 launches (one per class) per sweep, in place
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (kernel_ms) {
+      KK_HIP(hipEventCreate(&ev[0]));
+      KK_HIP(hipEventCreate(&ev[1]));
+      KK_HIP(hipEventRecord(ev[0], h->stream));
+    }
+    if (n > 0) h->epoch += 1;
+    for (uint64_t k = 0; k < n; ++k) {
+      for (int ph = 0; ph < 16; ++ph)
+        KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->k0, h->k1, h->t, ph, h->tacc,
+                                h->partials, h->stream));
+      h->t += 1;
+      h->attempts += (uint64_t)h->L * (uint64_t)h->L;
+    }
+    if (kernel_ms) {
+      KK_HIP(hipEventRecord(ev[1], h->stream));
+      KK_HIP(hipEventSynchronize(ev[1]));
+      float ms = 0.f;
+      KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      *kernel_ms = ms;
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+    }
+    if (launches) *launches = 16 * n;
+    return KK_OK;
+  }
   SweepParams p{};
   const int threads = tile_geometry(h->L, h->tile, &p);
   p.accepted = h->partials;
@@ -461,6 +489,45 @@ kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omeg
   return KK_OK;
 }
 
+kk_status kk_create_triangular(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed,
+                               void* hip_stream) {
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 4 || L % 8 != 4 || L > 32764)
+    return set_error(KK_EINVAL, "triangular lattice needs L %% 8 == 4 in [4, 32764] (got %u)", L);
+  kk_sim* h = nullptr;
+  kk_status st = kk_create_ex(&h, L, composition, omega_kT, seed, KK_LAYOUT_INT8, hip_stream);
+  if (st != KK_OK) return st;
+  h->geom = 1;
+  for (int n = 0; n <= 10; ++n) {
+    const double p = std::exp(-omega_kT * (double)(10 - 2 * n));
+    const double v = std::ceil(p * 4294967296.0);
+    h->tacc.T[n] = (v >= 4294967296.0) ? 4294967296ull : (uint64_t)v;
+  }
+  st = reset_partials(h);  // kTriPartials sums; nothing has been counted yet
+  if (st != KK_OK) {
+    kk_destroy(h);
+    return st;
+  }
+  *out = h;
+  return KK_OK;
+}
+
+kk_status kk_tri_thresholds(kk_sim* h, uint64_t out[11]) {
+  KK_GUARD(h);
+  if (!out) return set_error(KK_EINVAL, "out is NULL");
+  if (h->geom != 1) return set_error(KK_EINVAL, "square lattice: use kk_thresholds");
+  for (int i = 0; i < 11; ++i) out[i] = h->tacc.T[i];
+  return KK_OK;
+}
+
+kk_status kk_geometry(kk_sim* h, uint32_t* geometry) {
+  KK_GUARD(h);
+  if (!geometry) return set_error(KK_EINVAL, "geometry is NULL");
+  *geometry = (uint32_t)h->geom;
+  return KK_OK;
+}
+
 kk_status kk_sweep_async(kk_sim* h, uint64_t n) {
   KK_GUARD(h);
   return enqueue_sweeps(h, n, nullptr, nullptr);
@@ -495,7 +562,10 @@ kk_status kk_sweep_timed(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
 kk_status kk_energy(kk_sim* h, uint64_t* n_unlike, double* energy_kT) {
   KK_GUARD(h);
   KK_HIP(hipMemsetAsync(h->counters + 1, 0, sizeof(unsigned long long), h->stream));
-  KK_HIP(launch_energy(h->lat[h->cur], h->layout, h->L, h->counters + 1, h->stream));
+  if (h->geom == 1)
+    KK_HIP(launch_tri_energy(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->counters + 1, h->stream));
+  else
+    KK_HIP(launch_energy(h->lat[h->cur], h->layout, h->L, h->counters + 1, h->stream));
   unsigned long long v = 0;
   KK_HIP(hipMemcpyAsync(&v, h->counters + 1, sizeof v, hipMemcpyDeviceToHost, h->stream));
   KK_HIP(hipStreamSynchronize(h->stream));
@@ -526,7 +596,7 @@ kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap
     KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
     KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
     KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
-    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->stream));
+    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->geom == 1, h->stream));
     std::vector<unsigned> hs(kSmallSizes);
     unsigned nbig = 0;
     KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
@@ -563,9 +633,14 @@ kk_status kk_observe(kk_sim* h, int species, kk_observables* out) {
   kk_status st = kk_energy(h, &o.n_unlike, &o.energy_kT);
   if (st != KK_OK) return st;
   const uint64_t N = (uint64_t)h->L * (uint64_t)h->L;
-  o.similar_exact = 1.0 - (double)o.n_unlike / (double)(2 * N);
+  // the lattice has 2N bonds (square) or 3N (triangular)
+  o.similar_exact = 1.0 - (double)o.n_unlike / (double)((h->geom == 1 ? 3 : 2) * N);
   KK_HIP(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
-  KK_HIP(launch_similar_sampled(h->lat[h->cur], h->layout, h->L, h->k0, h->k1, h->t, h->counters, h->stream));
+  if (h->geom == 1)
+    KK_HIP(launch_tri_similar(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->k0, h->k1, h->t, h->counters,
+                              h->stream));
+  else
+    KK_HIP(launch_similar_sampled(h->lat[h->cur], h->layout, h->L, h->k0, h->k1, h->t, h->counters, h->stream));
   unsigned long long same = 0;
   KK_HIP(hipMemcpyAsync(&same, h->counters, sizeof same, hipMemcpyDeviceToHost, h->stream));
   KK_HIP(hipStreamSynchronize(h->stream));
@@ -665,6 +740,7 @@ kk_status kk_stats(kk_sim* h, uint64_t* sweeps, uint64_t* attempts, uint64_t* ac
 kk_status kk_thresholds(kk_sim* h, uint64_t out[7]) {
   KK_GUARD(h);
   if (!out) return set_error(KK_EINVAL, "out is NULL");
+  if (h->geom == 1) return set_error(KK_EINVAL, "triangular lattice: use kk_tri_thresholds (11 entries)");
   for (int i = 0; i < 7; ++i) out[i] = h->T[i];
   return KK_OK;
 }
@@ -678,6 +754,7 @@ kk_status kk_info(kk_sim* h, uint32_t* L, uint32_t* layout) {
 
 kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread) {
   KK_GUARD(h);
+  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   TileConfig tc{};
   tc.ku = (int)units_per_thread;
   if (tile_words == 0) {
@@ -698,6 +775,7 @@ kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32
 kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, uint32_t* tile_rows,
                       uint32_t* units_per_thread, double* us_per_sweep) {
   KK_GUARD(h);
+  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   if (trial_sweeps == 0) trial_sweeps = 20;
   if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
   const int L = h->L;
@@ -793,6 +871,7 @@ kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, ui
 
 kk_status kk_get_tile(kk_sim* h, uint32_t* tile_words, uint32_t* tile_rows, uint32_t* units_per_thread) {
   KK_GUARD(h);
+  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   if (tile_words) *tile_words = h->tile.cyclic ? 0u : (uint32_t)h->tile.tww;
   if (tile_rows) *tile_rows = (uint32_t)h->tile.th;
   if (units_per_thread) *units_per_thread = (uint32_t)h->tile.ku;

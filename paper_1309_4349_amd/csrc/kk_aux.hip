@@ -209,6 +209,23 @@ __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, in
   }
 }
 
+// Triangular lattice, helical boundaries (sites i = y*L + x on one ring of N):
+// unite i with i+1, i+L and i+L-1 (mod N) when both are of the species; the
+// other three of the six bonds are forward bonds of the neighbours.
+__global__ __launch_bounds__(256) void ccl_merge_tri(const uint8_t* lat, int L, int species, uint32_t* parent) {
+  const uint32_t N = (uint32_t)L * (uint32_t)L;
+  const uint32_t off[3] = {1u, (uint32_t)L, (uint32_t)L - 1u};
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    if (lat[i] != species) continue;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t j = i + off[k];
+      if (j >= N) j -= N;
+      if (lat[j] == species) unite(parent, i, j);
+    }
+  }
+}
+
 // After all unions: point every site straight at its root.
 __global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L) {
   const size_t n = (size_t)L * L;
@@ -332,11 +349,17 @@ hipError_t launch_set_sites(const uint32_t* idx, unsigned n, int L, int layout, 
   return hipGetLastError();
 }
 
-hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, hipStream_t stream) {
+hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, bool triangular,
+                      hipStream_t stream) {
   const size_t n = (size_t)L * L;
   const int g = grid_for(n, 256);
   hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
-  hipLaunchKernelGGL(ccl_merge, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  if (triangular) {
+    hipLaunchKernelGGL(ccl_merge_tri, dim3(g), dim3(256), 0, stream, static_cast<const uint8_t*>(lat), L, species,
+                       b.parent);
+  } else {
+    hipLaunchKernelGGL(ccl_merge, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  }
   hipLaunchKernelGGL(ccl_flatten, dim3(g), dim3(256), 0, stream, b.parent, L);
   hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, b.size);
   hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, b.hist, b.big,

@@ -52,6 +52,8 @@ struct kk_sim {
   kk::TileConfig tile{};
   kk::CclBuffers ccl{};
   bool ccl_ready = false;
+  int geom = 0;                          // 0: square torus; 1: triangular, helical (int8 ring)
+  kk::TriAccept tacc{};                  // triangular thresholds
   uint64_t epoch = 0;                    // bumped whenever the lattice may change
   uint64_t hist_epoch = ~(uint64_t)0;    // epoch and species of the cached histogram
   int hist_species = -1;

@@ -89,7 +89,20 @@ struct CclBuffers {
   unsigned big_cap;
 };
 constexpr int kSmallSizes = 4096;
-hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, hipStream_t stream);
+// triangular: six neighbours under helical boundaries (the int8 ring of kk_tri.hip).
+hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, bool triangular,
+                      hipStream_t stream);
+
+// Triangular lattice, helical boundaries (kk_tri.hip): one launch per phase.
+constexpr int kTriPartials = 64;  // accepted-move sums, indexed by workgroup % kTriPartials
+struct TriAccept {
+  uint64_t T[11];  // T[n] = min(2^32, ceil(exp(-omega (10 - 2n)) 2^32))
+};
+hipError_t launch_tri_phase(uint8_t* lat, int L, uint32_t k0, uint32_t k1, uint64_t t, int p, const TriAccept& acc,
+                            unsigned long long* partials, hipStream_t stream);
+hipError_t launch_tri_energy(const uint8_t* lat, int L, unsigned long long* out, hipStream_t stream);
+hipError_t launch_tri_similar(const uint8_t* lat, int L, uint32_t k0, uint32_t k1, uint64_t t,
+                              unsigned long long* out, hipStream_t stream);
 
 // int8 <-> bit-packed conversion on the device (bit-packed needs L % 32 == 0).
 hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stream);

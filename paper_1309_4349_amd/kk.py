@@ -20,7 +20,7 @@ LAYOUT_AUTO, LAYOUT_INT8, LAYOUT_BITPACKED = 0, 1, 2
 _LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPACKED}
 
 EXPORTS = [
-    "kk_create", "kk_create_ex", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
+    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_tri_thresholds", "kk_geometry", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
@@ -102,6 +102,9 @@ def load(path: str = LIB_PATH):
     sig = {
         "kk_create": [PP, U32, D, D, U64],
         "kk_create_ex": [PP, U32, D, D, U64, U32, P],
+        "kk_create_triangular": [PP, U32, D, D, U64, P],
+        "kk_tri_thresholds": [P, u64p],
+        "kk_geometry": [P, u32p],
         "kk_sweep": [P, U64],
         "kk_sweep_async": [P, U64],
         "kk_sync": [P],
@@ -156,14 +159,27 @@ def _check(st: int):
 
 
 class Sim:
-    """One lattice simulation owned by libkk (device memory and stream)."""
+    """One lattice simulation owned by libkk (device memory and stream).
+
+    geometry "square": the L x L torus (L % 4 == 0); "triangular": the paper's
+    six-neighbour lattice with helical boundaries (L % 8 == 4, int8 layout)."""
 
     def __init__(self, L: int, composition: float, omega: float, seed: int, layout: str = "auto",
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, geometry: str = "square"):
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.kk_create_ex(ctypes.byref(h), L, float(composition), float(omega), seed & (2**64 - 1),
-                                _LAYOUTS[layout], ctypes.c_void_p(stream) if stream else None))
+        st = ctypes.c_void_p(stream) if stream else None
+        if geometry == "square":
+            _check(lib.kk_create_ex(ctypes.byref(h), L, float(composition), float(omega), seed & (2**64 - 1),
+                                    _LAYOUTS[layout], st))
+        elif geometry == "triangular":
+            if layout not in ("auto", "int8"):
+                raise ValueError("the triangular lattice is stored one byte per site")
+            _check(lib.kk_create_triangular(ctypes.byref(h), L, float(composition), float(omega),
+                                            seed & (2**64 - 1), st))
+        else:
+            raise ValueError(f"unknown geometry {geometry!r}")
+        self.geometry = geometry
         self._h = h
         self.L = L
         self.omega = float(omega)
@@ -245,8 +261,11 @@ class Sim:
         return a.value, b.value, c.value
 
     def thresholds(self) -> np.ndarray:
-        out = np.zeros(7, dtype=np.uint64)
-        _check(load().kk_thresholds(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        """7 entries (square) or 11 (triangular)."""
+        tri = self.geometry == "triangular"
+        out = np.zeros(11 if tri else 7, dtype=np.uint64)
+        fn = load().kk_tri_thresholds if tri else load().kk_thresholds
+        _check(fn(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
         return out
 
     def info(self) -> Tuple[int, str]:

@@ -1,0 +1,85 @@
+"""GPU: the triangular lattice with helical boundaries (the paper's model)
+equals the oracle bit for bit -- lattice, accepted exchanges, N_AB, cluster
+histograms of both species and the observables -- over sizes from one site
+per class (L = 4) to many blocks with a ragged last one; runs resume exactly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_4349_amd import kk
+from paper_1309_4349_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("L,x,w,n", [
+    (4, 0.5, 0.4, 9), (12, 0.3, 1.1, 20), (20, 0.5, 0.8, 15), (100, 0.4, 1.0, 12),
+    (204, 0.5, 0.6, 6), (36, 0.0, 1.0, 3), (28, 1.0, 1.0, 3), (60, 0.5, -0.7, 8), (44, 0.5, 0.0, 5),
+])
+def test_tri_sweeps_match_oracle(L, x, w, n):
+    print(f"case tri L={L} x={x} w={w} n={n}", flush=True)
+    seed = wl.job_seed(41, L)
+    s = kk.Sim(L, x, w, seed, geometry="triangular")
+    ref = oracle.init(L, x, seed)
+    assert np.array_equal(s.get_lattice(), ref)
+    acc = oracle.tri_sweeps(ref, w, seed, 0, n)
+    s.sweep(n)
+    assert np.array_equal(s.get_lattice(), ref)
+    sw, att, got_acc = s.stats()
+    assert (sw, att, got_acc) == (n, n * L * L, acc)
+    assert s.energy()[0] == oracle.tri_energy(ref)
+    for species in (0, 1):
+        assert s.cluster_hist(species) == oracle.tri_cluster_hist(ref, species)
+        got = s.observe(species)
+        want = oracle.tri_observables(ref, w, species, seed, n)
+        for k, v in want.items():
+            assert got[k] == v, (species, k, got[k], v)
+    assert np.array_equal(s.thresholds(), oracle.tri_thresholds(w))
+    s.close()
+
+
+def test_tri_resume_and_series():
+    L, x, w, seed = 52, 0.45, 0.9, 123
+    a = kk.Sim(L, x, w, seed, geometry="triangular")
+    a.sweep(7)
+    snap = a.get_lattice()
+    a.sweep(11)
+    b = kk.Sim(L, x, w, seed + 1, geometry="triangular")
+    b.close()
+    b = kk.Sim(L, x, w, seed, geometry="triangular")
+    b.set_lattice(snap, 7)
+    b.sweep(11)
+    assert np.array_equal(a.get_lattice(), b.get_lattice())
+    c = kk.Sim(L, x, w, seed, geometry="triangular")
+    ser = c.series(every=6, count=3, species=1)
+    d = kk.Sim(L, x, w, seed, geometry="triangular")
+    for i in range(3):
+        d.sweep(6)
+        assert ser[i] == d.observe(1), i
+    for h in (a, b, c, d):
+        h.close()
+
+
+def test_tri_large_sampled_sites():
+    # a large ring: whole-lattice invariants plus a sampled recount of N_AB
+    L, x, w, seed = 1028, 0.5, 1.0, 99
+    s = kk.Sim(L, x, w, seed, geometry="triangular")
+    ref = oracle.init(L, x, seed)
+    oracle.tri_sweeps(ref, w, seed, 0, 4)
+    s.sweep(4)
+    got = s.get_lattice()
+    assert np.array_equal(got, ref)
+    assert int(got.sum()) == oracle.n_ones(L, x)
+    assert s.energy()[0] == oracle.tri_energy(ref)
+    s.close()
+
+
+def test_tri_rejects_square_only_calls():
+    s = kk.Sim(12, 0.5, 1.0, 1, geometry="triangular")
+    for call in (lambda: s.get_tile(), lambda: s.set_tile(8, 64, 1), lambda: s.autotune(2)):
+        with pytest.raises(kk.KKError):
+            call()
+    s.close()
+    for L in (8, 16, 0, 6):
+        with pytest.raises(kk.KKError):
+            kk.Sim(L, 0.5, 1.0, 1, geometry="triangular")

@@ -212,3 +212,21 @@ def test_sweeps_conserve_composition_and_are_deterministic(orc):
     orc.tri_sweeps(c, 0.7, 5, 0, 12)
     orc.tri_sweeps(c, 0.7, 5, 12, 18)   # split runs resume exactly
     assert np.array_equal(a, c)
+
+
+def test_observables_of_special_lattices(orc):
+    L = 12
+    N = L * L
+    o = orc.tri_observables(np.ones((L, L), np.uint8), 0.5, 1, 3, 0)
+    assert (o["n_unlike"], o["similar_exact"], o["similar_sampled"]) == (0, 1.0, 1.0)
+    assert (o["n_clusters"], o["size_max"], o["size_number_avg"], o["size_weight_avg"]) == (1, N, N, N)
+    # isolated type-1 sites: one schedule class (no two of its sites are neighbours)
+    s = np.zeros(N, np.uint8)
+    s[::16] = 1                        # a class: no two of its sites are neighbours
+    o = orc.tri_observables(s.reshape(L, L), 1.0, 1, 3, 0)
+    k = N // 16
+    assert o["n_unlike"] == 6 * k and o["energy_kT"] == 6.0 * k
+    assert o["similar_exact"] == 1.0 - 6 * k / (3 * N)
+    assert (o["n_clusters"], o["size_max"], o["size_number_avg"], o["size_weight_avg"]) == (k, 1, 1.0, 1.0)
+    o0 = orc.tri_observables(s.reshape(L, L), 1.0, 0, 3, 0)
+    assert o0["n_clusters"] == 1 and o0["size_max"] == N - k
