@@ -13,7 +13,10 @@ histogram of species 1.  The line also carries:
     replicas run one after another through the plain path;
   * grid_400 -- the 12-run 400x400 grid batched, histograms every 1000 sweeps;
   * serving -- p50/p99 latency, served and offered attempts/s of the job
-    server replaying the Poisson job trace, saturated and below saturation.
+    server replaying the Poisson job trace, saturated and below saturation;
+  * triangular -- the paper's own six-neighbour helical lattice (4092^2,
+    int8): attempts/s, the phase kernel's time per launch and its roofline,
+    with the triangular CPU oracle timed beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -92,6 +95,63 @@ def cpu_baseline(job, budget_s: float = 12.0):
     return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} sweeps of the {job.L}x{job.L} x={job.composition} omega={job.omega} lattice "
                       f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})"}
+
+
+# Algorithmic cost of one attempt of the triangular phase kernel, in 32-bit VALU
+# lane-ops: one Philox4x32-10 block per centre (40, as above), the partner
+# direction and uniform (3), 12 neighbour indices on the ring (2 each, 24),
+# 12 unlike tests and their sum (24), the threshold lookup and compare (3),
+# the swap (2) -> 96.  Algorithmic bytes: each site read and written once per
+# sweep (2 B); the neighbour reads of the 16 phases hit the caches.
+TRI_OPS_PER_ATTEMPT = 96.0
+
+
+def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
+    """Attempts/s of the triangular helical lattice (the paper's geometry)."""
+    import torch
+
+    import oracle
+    from paper_1309_4349_amd import kk
+
+    L, x, w, seed = 4092, 0.5, 0.88, 0x13094349
+    N = L * L
+    sim = kk.Sim(L, x, w, seed, geometry="triangular")
+    sim.sweep(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(sweeps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = sweeps * N / dt
+    ms, launches = sim.sweep_timed(profile_sweeps)
+    per_launch_s = ms / 1e3 / launches
+    per_launch = N * profile_sweeps / launches
+    ops = TRI_OPS_PER_ATTEMPT * per_launch / per_launch_s / 1e9
+    hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
+    nab, _ = sim.energy()
+    sim.close()
+    out = {"workload": f"triangular helical {L}x{L} int8, x={x}, omega={w}, {sweeps} sweeps",
+           "value": rate, "unit": "attempts/s", "n_unlike_over_3N": nab / (3 * N),
+           "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
+                        "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
+                        "traffic": None, "kernel": "tri_phase", "kernel_us": round(per_launch_s * 1e6, 3),
+                        "launches": int(launches), "ops_per_attempt": TRI_OPS_PER_ATTEMPT,
+                        "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
+    log(f"[bench] triangular {L}^2: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
+    if cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        s = oracle.init(L, x, seed)
+        t0 = time.perf_counter()
+        oracle.tri_sweeps(s, w, seed, 0, 1)
+        one = time.perf_counter() - t0
+        n = max(1, int(8.0 / max(one, 1e-3)) - 1)
+        t0 = time.perf_counter()
+        oracle.tri_sweeps(s, w, seed, 1, n)
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * N / dtc, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{n} sweeps of the same {L}x{L} triangular lattice ({dtc:.1f} s)"}
+        log(f"[bench] triangular oracle {n * N / dtc:.3e} attempts/s on {threads} threads")
+    return out
 
 
 def batched_vs_plain(sweeps: int, plain_sweeps: int):
@@ -223,6 +283,8 @@ def main():
     ap.add_argument("--serve-light-rate", type=float, default=5.0, help="arrival rate of the below-saturation trace")
     ap.add_argument("--serve-chunk", type=int, default=1000, help="sweeps per server step")
     ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
+    ap.add_argument("--no-tri", action="store_true", help="skip the triangular-lattice measurement")
+    ap.add_argument("--tri-sweeps", type=int, default=500, help="sweeps of the 4092^2 triangular lattice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -321,6 +383,10 @@ def main():
     if not args.no_serve:
         served = serving(args.serve_jobs, args.serve_light_jobs, args.serve_light_rate, args.serve_chunk)
 
+    tri = None
+    if not args.no_tri:
+        tri = triangular(args.tri_sweeps, 100, not args.no_cpu)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
@@ -347,6 +413,8 @@ def main():
         line["grid_400"] = grid
     if served is not None:
         line["serving"] = served
+    if tri is not None:
+        line["triangular"] = tri
     print(json.dumps(line), flush=True)
 
 

@@ -112,6 +112,19 @@ kk_status kk_tri_thresholds(kk_sim *h, uint64_t out[11]);
 /* 0 for the square torus, 1 for the triangular helical lattice. */
 kk_status kk_geometry(kk_sim *h, uint32_t *geometry);
 
+/* Starting configurations (Results, "MPKK vs. Kawasaki method" and "Cluster
+ * Analysis", Figs. 10-11: random against non-random starts). */
+enum {
+    KK_START_RANDOM = 0,     /* the seeded uniform random subset of kk_create */
+    KK_START_SEGREGATED = 1  /* the first n1 sites in index order i = y*L + x hold type 1: full rows
+                                0 .. n1/L - 1 and the first n1 % L sites of the next row */
+};
+
+/* Put the handle back at a starting configuration of the same size,
+ * composition and seed: the lattice is replaced, the sweep counter, attempts
+ * and accepted count return to 0.  Works on both geometries and layouts. */
+kk_status kk_restart(kk_sim *h, uint32_t start);
+
 /* Run n_sweeps sweeps (N attempts each, the paper's MPKK step), t .. t+n-1,
  * and wait for them.  Advances the sweep counter. */
 kk_status kk_sweep(kk_sim *h, uint64_t n_sweeps);

@@ -37,7 +37,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -62,6 +62,7 @@ def _load():
         "ko_init": (ctypes.c_int, [u8p, U32, D, U64]),
         "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
         "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
+        "ko_tri_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
         "ko_similar_sampled": (U64, [u8p, U32, U64, U64]),
         "ko_tri_thresholds": (None, [D, u64p]),
         "ko_tri_phase_order": (None, [U64, U64, c_int_p]),
@@ -290,6 +291,20 @@ def tri_observables(s: np.ndarray, omega: float, species: int, seed: int, t: int
     N = s.shape[0] * s.shape[0]
     return _observables_of(tri_energy(s), 3 * N, tri_cluster_counts(s, species), tri_similar_sampled(s, seed, t),
                            N, omega)
+
+
+def init_segregated(L: int, composition: float) -> np.ndarray:
+    """The non-random start (Results, Figs. 10-11), read as full segregation:
+    the first n1 sites in index order y*L + x hold type 1."""
+    s = np.zeros(L * L, dtype=np.uint8)
+    s[: n_ones(L, composition)] = 1
+    return s.reshape(L, L)
+
+
+def tri_seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:
+    """Sequential random-site Kawasaki on the triangular helical lattice."""
+    s = _lattice(s)
+    return int(_load().ko_tri_seq_kawasaki(_ptr(s, ctypes.c_uint8), s.shape[0], float(omega), rng_seed, n_steps))
 
 
 def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:

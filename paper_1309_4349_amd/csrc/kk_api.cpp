@@ -513,6 +513,25 @@ kk_status kk_create_triangular(kk_sim** out, uint32_t L, double composition, dou
   return KK_OK;
 }
 
+kk_status kk_restart(kk_sim* h, uint32_t start) {
+  KK_GUARD(h);
+  if (start != KK_START_RANDOM && start != KK_START_SEGREGATED)
+    return set_error(KK_EINVAL, "unknown start %u", start);
+  if (start == KK_START_RANDOM) {
+    const kk_status st = place_initial(h);
+    if (st != KK_OK) return st;
+  } else {
+    KK_HIP(launch_fill_segregated(h->lat[h->cur], h->layout, h->L, place_count(h->L, h->composition), h->stream));
+  }
+  KK_HIP(hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream));
+  KK_HIP(hipStreamSynchronize(h->stream));
+  h->t = 0;
+  h->attempts = 0;
+  h->accepted_base = 0;
+  h->epoch += 1;
+  return KK_OK;
+}
+
 kk_status kk_tri_thresholds(kk_sim* h, uint64_t out[11]) {
   KK_GUARD(h);
   if (!out) return set_error(KK_EINVAL, "out is NULL");

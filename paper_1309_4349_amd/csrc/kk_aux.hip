@@ -209,6 +209,24 @@ __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, in
   }
 }
 
+// Segregated start: the first n1 sites in index order i = y*L + x hold type 1
+// (full rows 0 .. n1/L - 1 and the start of the next one).  Bit-packed words
+// tile rows exactly, so word w holds sites 32w .. 32w + 31.
+__global__ __launch_bounds__(256) void fill_segregated(void* lat, int layout, int L, uint64_t n1) {
+  const size_t n = (size_t)L * L;
+  if (layout == kLayoutBits) {
+    uint32_t* w = static_cast<uint32_t*>(lat);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n / 32; i += (size_t)gridDim.x * blockDim.x) {
+      const uint64_t lo = 32 * (uint64_t)i;
+      w[i] = n1 >= lo + 32 ? 0xFFFFFFFFu : (n1 <= lo ? 0u : ((1u << (uint32_t)(n1 - lo)) - 1u));
+    }
+  } else {
+    uint8_t* b = static_cast<uint8_t*>(lat);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+      b[i] = (uint64_t)i < n1 ? 1 : 0;
+  }
+}
+
 // Triangular lattice, helical boundaries (sites i = y*L + x on one ring of N):
 // unite i with i+1, i+L and i+L-1 (mod N) when both are of the species; the
 // other three of the six bonds are forward bonds of the neighbours.
@@ -374,6 +392,11 @@ hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stre
 
 hipError_t launch_unpack(const uint32_t* in, uint8_t* out, int L, hipStream_t stream) {
   hipLaunchKernelGGL(unpack_bits, dim3(grid_for((size_t)L * (L >> 5), 256)), dim3(256), 0, stream, in, out, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_segregated(void* lat, int layout, int L, uint64_t n1, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_segregated, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream, lat, layout, L, n1);
   return hipGetLastError();
 }
 

@@ -104,6 +104,9 @@ hipError_t launch_tri_energy(const uint8_t* lat, int L, unsigned long long* out,
 hipError_t launch_tri_similar(const uint8_t* lat, int L, uint32_t k0, uint32_t k1, uint64_t t,
                               unsigned long long* out, hipStream_t stream);
 
+// Segregated start: sites 0 .. n1-1 (index y*L + x) set to 1, the rest 0.
+hipError_t launch_fill_segregated(void* lat, int layout, int L, uint64_t n1, hipStream_t stream);
+
 // int8 <-> bit-packed conversion on the device (bit-packed needs L % 32 == 0).
 hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stream);
 hipError_t launch_unpack(const uint32_t* in, uint8_t* out, int L, hipStream_t stream);

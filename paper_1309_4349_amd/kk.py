@@ -18,9 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libkk.so")
 KK_OK, KK_EINVAL, KK_ENOMEM, KK_EDEVICE, KK_ESTATE, KK_ETRUNC = range(6)
 LAYOUT_AUTO, LAYOUT_INT8, LAYOUT_BITPACKED = 0, 1, 2
 _LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPACKED}
+START_RANDOM, START_SEGREGATED = 0, 1
+_STARTS = {"random": START_RANDOM, "segregated": START_SEGREGATED}
 
 EXPORTS = [
-    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_tri_thresholds", "kk_geometry", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
+    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_tri_thresholds", "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
@@ -105,6 +107,7 @@ def load(path: str = LIB_PATH):
         "kk_create_triangular": [PP, U32, D, D, U64, P],
         "kk_tri_thresholds": [P, u64p],
         "kk_geometry": [P, u32p],
+        "kk_restart": [P, U32],
         "kk_sweep": [P, U64],
         "kk_sweep_async": [P, U64],
         "kk_sync": [P],
@@ -201,6 +204,10 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+    def restart(self, start: str = "random"):
+        """Back to a starting lattice ("random" or "segregated"), t = 0."""
+        _check(load().kk_restart(self._h, _STARTS[start]))
 
     # -- the path -------------------------------------------------------------
     def sweep(self, n: int):
