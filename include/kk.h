@@ -106,10 +106,43 @@ kk_status kk_create_ex(kk_sim **out, uint32_t L, double composition, double omeg
 kk_status kk_create_triangular(kk_sim **out, uint32_t L, double composition, double omega_kT, uint64_t seed,
                                void *hip_stream);
 
+/* Triangular schemes for kk_create_triangular_ex. */
+enum {
+    KK_TRI_CLASSES = 0, /* the conflict-free 16-class schedule of kk_create_triangular */
+    KK_TRI_MPKK = 1     /* the paper's literal MPKK (Materials and Methods, "Massive Parallel Kawasaki
+                           Kinetics", Fig. 4), a comparison variant */
+};
+
+/* A triangular helical lattice of H rows of L sites (N = L*H, i = y*L + x on
+ * one ring; neighbours i +- 1, i +- L, i +- (L-1) mod N), int8, placed as
+ * kk_create's random start (Philox init keys addressed by (y, x)).
+ * KK_TRI_CLASSES: as kk_create_triangular; needs L % 8 == 4 and H % 4 == 0.
+ * KK_TRI_MPKK: needs L % 7 in {3, 5} and H % 7 == 0, so that the 7-site domains
+ *   (a centre and its six neighbours) centred on c = k (mod 7) partition the
+ *   ring for every k.  One "sweep" is one MPKK step of 7 iterations; iteration
+ *   j draws k_j = (w * 7) >> 32 from word j%4 of Philox block (j/4, 2, t_lo,
+ *   t_hi28 | 8<<28), with replacement, and makes one attempt in every domain
+ *   m (centre k_j + 7m): direction d = (w * 6) >> 32 from word 2(m%2) and U
+ *   from word 2(m%2)+1 of block (m/2, j, t_lo, t_hi28 | 9<<28), accepted iff
+ *   U < T[n] as above.  All domains of an iteration decide from the lattice as
+ *   it stood when the iteration began and their exchanges are applied
+ *   together (the domains are disjoint): the paper's simultaneous update,
+ *   whose decisions may read sites that a neighbouring domain exchanges.  N
+ *   attempts per step.
+ * Both need N <= 2^32 - 16 and L, H <= 65535.  Energy, clusters,
+ * observables, lattice copies, restart and stats work as for
+ * kk_create_triangular; kk_get_lattice/kk_set_lattice take N = L*H bytes. */
+kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t scheme, double composition,
+                                  double omega_kT, uint64_t seed, void *hip_stream);
+
+/* Sites per row and rows (H == L except for kk_create_triangular_ex). */
+kk_status kk_shape(kk_sim *h, uint32_t *L, uint32_t *H);
+
 /* The 11 thresholds T[0..10] of a triangular handle (KK_EINVAL on a square one). */
 kk_status kk_tri_thresholds(kk_sim *h, uint64_t out[11]);
 
-/* 0 for the square torus, 1 for the triangular helical lattice. */
+/* 0 for the square torus, 1 for the triangular helical lattice with the
+ * conflict-free classes, 2 for the triangular lattice under literal MPKK. */
 kk_status kk_geometry(kk_sim *h, uint32_t *geometry);
 
 /* Starting configurations (Results, "MPKK vs. Kawasaki method" and "Cluster

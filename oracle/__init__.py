@@ -60,18 +60,24 @@ def _load():
         "ko_n_ones": (U64, [U32, D]),
         "ko_init_key": (U64, [U64, U32, U32]),
         "ko_init": (ctypes.c_int, [u8p, U32, D, U64]),
+        "ko_init_rect": (ctypes.c_int, [u8p, U32, U32, D, U64]),
+        "ko_n_ones_rect": (U64, [U32, U32, D]),
         "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
         "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
-        "ko_tri_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
+        "ko_tri_seq_kawasaki": (U64, [u8p, U32, U32, D, U64, U64]),
+        "ko_mpkk_k": (ctypes.c_int, [U64, U64, ctypes.c_int]),
+        "ko_mpkk_domain_randoms": (None, [U64, U64, ctypes.c_int, U64, u32p, u32p]),
+        "ko_mpkk_iteration": (ctypes.c_int64, [u8p, U32, U32, ctypes.c_int, u32p, u32p, u64p]),
+        "ko_mpkk_steps": (U64, [u8p, U32, U32, D, U64, U64, U64]),
         "ko_similar_sampled": (U64, [u8p, U32, U64, U64]),
         "ko_tri_thresholds": (None, [D, u64p]),
         "ko_tri_phase_order": (None, [U64, U64, c_int_p]),
         "ko_tri_site_randoms": (None, [U64, U64, U64, u32p, u32p]),
-        "ko_tri_local_dnab": (ctypes.c_int, [u8p, U32, U64, U32]),
-        "ko_tri_sweeps": (U64, [u8p, U32, D, U64, U64, U64]),
-        "ko_tri_energy": (U64, [u8p, U32]),
-        "ko_tri_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
-        "ko_tri_similar_sampled": (U64, [u8p, U32, U64, U64]),
+        "ko_tri_local_dnab": (ctypes.c_int, [u8p, U32, U32, U64, U32]),
+        "ko_tri_sweeps": (U64, [u8p, U32, U32, D, U64, U64, U64]),
+        "ko_tri_energy": (U64, [u8p, U32, U32]),
+        "ko_tri_cluster_counts": (U64, [u8p, U32, U32, ctypes.c_int, u64p]),
+        "ko_tri_similar_sampled": (U64, [u8p, U32, U32, U64, U64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -83,6 +89,13 @@ def _load():
 
 def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _ring(s: np.ndarray) -> np.ndarray:
+    """A triangular helical lattice: H rows of L sites, shape (H, L)."""
+    if s.dtype != np.uint8 or s.ndim != 2 or not s.flags.c_contiguous:
+        raise ValueError("lattice must be a C-contiguous 2-D uint8 array")
+    return s
 
 
 def _lattice(s: np.ndarray) -> np.ndarray:
@@ -171,6 +184,18 @@ def init(L: int, composition: float, seed: int) -> np.ndarray:
     return s
 
 
+def n_ones_rect(L: int, H: int, composition: float) -> int:
+    return int(_load().ko_n_ones_rect(L, H, float(composition)))
+
+
+def init_rect(L: int, H: int, composition: float, seed: int) -> np.ndarray:
+    """The random start on H rows of L sites (shape (H, L))."""
+    s = np.zeros((H, L), dtype=np.uint8)
+    if _load().ko_init_rect(_ptr(s, ctypes.c_uint8), L, H, float(composition), seed) != 0:
+        raise MemoryError("oracle init allocation failed")
+    return s
+
+
 def cluster_counts(s: np.ndarray, species: int = 1) -> np.ndarray:
     """Dense counts: out[k] = number of clusters of exactly k sites."""
     s = _lattice(s)
@@ -249,25 +274,25 @@ def tri_site_randoms(seed: int, t: int, i: int):
 
 
 def tri_local_dnab(s: np.ndarray, i: int, direction: int) -> int:
-    s = _lattice(s)
-    return int(_load().ko_tri_local_dnab(_ptr(s, ctypes.c_uint8), s.shape[0], i, direction))
+    s = _ring(s)
+    return int(_load().ko_tri_local_dnab(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], i, direction))
 
 
 def tri_sweeps(s: np.ndarray, omega: float, seed: int, t0: int, n: int) -> int:
-    s = _lattice(s)
-    return int(_load().ko_tri_sweeps(_ptr(s, ctypes.c_uint8), s.shape[0], float(omega), seed, t0, n))
+    s = _ring(s)
+    return int(_load().ko_tri_sweeps(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], float(omega), seed, t0, n))
 
 
 def tri_energy(s: np.ndarray) -> int:
-    s = _lattice(s)
-    return int(_load().ko_tri_energy(_ptr(s, ctypes.c_uint8), s.shape[0]))
+    s = _ring(s)
+    return int(_load().ko_tri_energy(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0]))
 
 
 def tri_cluster_counts(s: np.ndarray, species: int = 1) -> np.ndarray:
-    s = _lattice(s)
-    L = s.shape[0]
-    counts = np.zeros(L * L + 1, dtype=np.uint64)
-    r = _load().ko_tri_cluster_counts(_ptr(s, ctypes.c_uint8), L, int(species), _ptr(counts, ctypes.c_uint64))
+    s = _ring(s)
+    H, L = s.shape
+    counts = np.zeros(L * H + 1, dtype=np.uint64)
+    r = _load().ko_tri_cluster_counts(_ptr(s, ctypes.c_uint8), L, H, int(species), _ptr(counts, ctypes.c_uint64))
     if r == 2**64 - 1:
         raise MemoryError("oracle cluster allocation failed")
     return counts
@@ -280,31 +305,73 @@ def tri_cluster_hist(s: np.ndarray, species: int = 1):
 
 
 def tri_similar_sampled(s: np.ndarray, seed: int, t: int) -> int:
-    s = _lattice(s)
-    return int(_load().ko_tri_similar_sampled(_ptr(s, ctypes.c_uint8), s.shape[0], seed, t))
+    s = _ring(s)
+    return int(_load().ko_tri_similar_sampled(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], seed, t))
 
 
 def tri_observables(s: np.ndarray, omega: float, species: int, seed: int, t: int) -> dict:
     """observables() on the triangular lattice: 3N bonds, six-connected
     clusters, the six-neighbour random draw."""
-    s = _lattice(s)
-    N = s.shape[0] * s.shape[0]
+    s = _ring(s)
+    N = s.shape[0] * s.shape[1]
     return _observables_of(tri_energy(s), 3 * N, tri_cluster_counts(s, species), tri_similar_sampled(s, seed, t),
                            N, omega)
 
 
-def init_segregated(L: int, composition: float) -> np.ndarray:
+def init_segregated(L: int, composition: float, H: int = 0) -> np.ndarray:
     """The non-random start (Results, Figs. 10-11), read as full segregation:
-    the first n1 sites in index order y*L + x hold type 1."""
-    s = np.zeros(L * L, dtype=np.uint8)
-    s[: n_ones(L, composition)] = 1
-    return s.reshape(L, L)
+    the first n1 sites in index order y*L + x hold type 1 (H rows; 0 = L)."""
+    H = H or L
+    s = np.zeros(L * H, dtype=np.uint8)
+    s[: n_ones_rect(L, H, composition)] = 1
+    return s.reshape(H, L)
 
 
 def tri_seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:
     """Sequential random-site Kawasaki on the triangular helical lattice."""
-    s = _lattice(s)
-    return int(_load().ko_tri_seq_kawasaki(_ptr(s, ctypes.c_uint8), s.shape[0], float(omega), rng_seed, n_steps))
+    s = _ring(s)
+    return int(_load().ko_tri_seq_kawasaki(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], float(omega), rng_seed,
+                                            n_steps))
+
+
+# --------------------------------------------------------------------------
+# The paper's literal MPKK: 7-site domains covering H rows of L sites
+# (L = 3 or 5 mod 7, H = 0 mod 7), 7 iterations per step with k drawn with
+# replacement, every domain of an iteration deciding from the state at its
+# start.
+# --------------------------------------------------------------------------
+def mpkk_k(seed: int, t: int, j: int) -> int:
+    return int(_load().ko_mpkk_k(seed, t, j))
+
+
+def mpkk_domain_randoms(seed: int, t: int, j: int, m: int):
+    d, u = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().ko_mpkk_domain_randoms(seed, t, j, m, ctypes.byref(d), ctypes.byref(u))
+    return d.value, u.value
+
+
+def mpkk_iteration(s: np.ndarray, k: int, dirs, us, T) -> int:
+    """One synchronous iteration with explicit directions and uniforms (one per domain)."""
+    s = _ring(s)
+    M = s.size // 7
+    d = np.ascontiguousarray(dirs, dtype=np.uint32)
+    u = np.ascontiguousarray(us, dtype=np.uint32)
+    T = np.ascontiguousarray(T, dtype=np.uint64)
+    if d.shape != (M,) or u.shape != (M,) or T.shape != (11,):
+        raise ValueError("need one direction and one uniform per domain and 11 thresholds")
+    r = _load().ko_mpkk_iteration(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], int(k), _ptr(d, ctypes.c_uint32),
+                                  _ptr(u, ctypes.c_uint32), _ptr(T, ctypes.c_uint64))
+    if r < 0:
+        raise MemoryError("oracle allocation failed")
+    return int(r)
+
+
+def mpkk_steps(s: np.ndarray, omega: float, seed: int, t0: int, n: int) -> int:
+    s = _ring(s)
+    r = _load().ko_mpkk_steps(_ptr(s, ctypes.c_uint8), s.shape[1], s.shape[0], float(omega), seed, t0, n)
+    if r == 2**64 - 1:
+        raise MemoryError("oracle allocation failed")
+    return int(r)
 
 
 def seq_kawasaki(s: np.ndarray, omega: float, rng_seed: int, n_steps: int) -> int:

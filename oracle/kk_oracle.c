@@ -420,15 +420,20 @@ static int cmp_keyed(const void *a, const void *b)
     return 0;
 }
 
-uint64_t ko_n_ones(uint32_t L, double composition)
+uint64_t ko_n_ones_rect(uint32_t L, uint32_t H, double composition)
 {
-    double N = (double)L * (double)L;
+    double N = (double)L * (double)H;
     double v = floor(composition * N + 0.5);
     if (v < 0.0)
         v = 0.0;
     if (v > N)
         v = N;
     return (uint64_t)v;
+}
+
+uint64_t ko_n_ones(uint32_t L, double composition)
+{
+    return ko_n_ones_rect(L, L, composition);
 }
 
 uint64_t ko_init_key(uint64_t seed, uint32_t x, uint32_t y)
@@ -443,10 +448,11 @@ uint64_t ko_init_key(uint64_t seed, uint32_t x, uint32_t y)
     return ((uint64_t)out[0] << 32) | (uint64_t)out[1];
 }
 
-int ko_init(uint8_t *s, uint32_t L, double composition, uint64_t seed)
+/* H rows of L sites (the square lattice is H = L). */
+int ko_init_rect(uint8_t *s, uint32_t L, uint32_t H, double composition, uint64_t seed)
 {
-    size_t N = (size_t)L * L, i;
-    uint64_t n1 = ko_n_ones(L, composition);
+    size_t N = (size_t)L * H, i;
+    uint64_t n1 = ko_n_ones_rect(L, H, composition);
     ko_keyed *ks = (ko_keyed *)malloc(N * sizeof(ko_keyed));
     if (!ks)
         return -1;
@@ -460,6 +466,11 @@ int ko_init(uint8_t *s, uint32_t L, double composition, uint64_t seed)
         s[ks[i].idx] = 1;
     free(ks);
     return 0;
+}
+
+int ko_init(uint8_t *s, uint32_t L, double composition, uint64_t seed)
+{
+    return ko_init_rect(s, L, L, composition, seed);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -609,12 +620,13 @@ uint64_t ko_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_seed
 /* kinetics", Fig. 2, and "Cluster Analysis methods": six neighbours under */
 /* helical boundaries).                                                    */
 /*                                                                         */
-/* Sites i = y*L + x, 0 <= i < N = L*L, form one ring: the neighbours of i */
-/* are i +- 1, i +- L and i +- (L - 1) modulo N (the last site of a row is */
-/* followed by the first of the next).  Schedule: class(i) = i mod 16;     */
-/* for L = 4 (mod 8) two sites of one class are at least 4 steps apart, so */
-/* no exchange of a class reads a site another one writes.  A sweep visits */
-/* the 16 classes in a random order.                                       */
+/* H rows of L sites, i = y*L + x, 0 <= i < N = L*H, form one ring: the   */
+/* neighbours of i are i +- 1, i +- L and i +- (L - 1) modulo N (the last  */
+/* site of a row is followed by the first of the next).  Schedule:         */
+/* class(i) = i mod 16; for L = 4 (mod 8) and H = 0 (mod 4) two sites of   */
+/* one class are at least 4 steps apart, so no exchange of a class reads a */
+/* site another one writes.  A sweep visits the 16 classes in a random     */
+/* order.  The paper's square lattices are H = L.                          */
 /* Random numbers (Philox4x32-10, key = seed):                             */
 /*   site i at sweep t: block (i div 2, 0, t_lo, t_hi28 | 6<<28), words     */
 /*   2(i mod 2) (direction) and 2(i mod 2) + 1 (uniform U);                 */
@@ -693,9 +705,9 @@ void ko_tri_site_randoms(uint64_t seed, uint64_t t, uint64_t i, uint32_t *dir, u
     *u = b[2 * (i & 1u) + 1];
 }
 
-static int tri_unlike_except(const uint8_t *s, uint32_t L, uint64_t i, uint64_t other)
+static int tri_unlike_except(const uint8_t *s, uint32_t L, uint32_t H, uint64_t i, uint64_t other)
 {
-    uint64_t N = (uint64_t)L * L;
+    uint64_t N = (uint64_t)L * H;
     uint32_t d;
     int n = 0;
     for (d = 0; d < 6; ++d) {
@@ -706,17 +718,18 @@ static int tri_unlike_except(const uint8_t *s, uint32_t L, uint64_t i, uint64_t 
 }
 
 /* dN_AB of exchanging site i with its neighbour in direction d (0 when alike). */
-int ko_tri_local_dnab(const uint8_t *s, uint32_t L, uint64_t i, uint32_t d)
+int ko_tri_local_dnab(const uint8_t *s, uint32_t L, uint32_t H, uint64_t i, uint32_t d)
 {
-    uint64_t N = (uint64_t)L * L;
+    uint64_t N = (uint64_t)L * H;
     uint64_t b = tri_nb(i, tri_offset(L, d), N);
     if (s[i] == s[b]) return 0;
-    return 10 - 2 * (tri_unlike_except(s, L, i, b) + tri_unlike_except(s, L, b, i));
+    return 10 - 2 * (tri_unlike_except(s, L, H, i, b) + tri_unlike_except(s, L, H, b, i));
 }
 
-uint64_t ko_tri_sweeps(uint8_t *s, uint32_t L, double omega, uint64_t seed, uint64_t t0, uint64_t n_sweeps)
+uint64_t ko_tri_sweeps(uint8_t *s, uint32_t L, uint32_t H, double omega, uint64_t seed, uint64_t t0,
+                       uint64_t n_sweeps)
 {
-    uint64_t T[11], N = (uint64_t)L * L, acc = 0, t;
+    uint64_t T[11], N = (uint64_t)L * H, acc = 0, t;
     int perm[16], p;
     ko_tri_thresholds(omega, T);
     for (t = t0; t < t0 + n_sweeps; ++t) {
@@ -732,7 +745,7 @@ uint64_t ko_tri_sweeps(uint8_t *s, uint32_t L, double omega, uint64_t seed, uint
                 ko_tri_site_randoms(seed, t, (uint64_t)i, &d, &u);
                 b = tri_nb((uint64_t)i, tri_offset(L, d), N);
                 if (s[i] != s[b]) {
-                    int n = tri_unlike_except(s, L, (uint64_t)i, b) + tri_unlike_except(s, L, b, (uint64_t)i);
+                    int n = tri_unlike_except(s, L, H, (uint64_t)i, b) + tri_unlike_except(s, L, H, b, (uint64_t)i);
                     if ((uint64_t)u < T[n]) {
                         uint8_t tmp = s[i];
                         s[i] = s[b];
@@ -748,9 +761,9 @@ uint64_t ko_tri_sweeps(uint8_t *s, uint32_t L, double omega, uint64_t seed, uint
 }
 
 /* N_AB over the 3N bonds (i, i+1), (i, i+L), (i, i+L-1). */
-uint64_t ko_tri_energy(const uint8_t *s, uint32_t L)
+uint64_t ko_tri_energy(const uint8_t *s, uint32_t L, uint32_t H)
 {
-    uint64_t N = (uint64_t)L * L, i, nab = 0;
+    uint64_t N = (uint64_t)L * H, i, nab = 0;
     for (i = 0; i < N; ++i) {
         nab += (s[i] != s[tri_nb(i, 1, N)]);
         nab += (s[i] != s[tri_nb(i, (int64_t)L, N)]);
@@ -760,9 +773,9 @@ uint64_t ko_tri_energy(const uint8_t *s, uint32_t L)
 }
 
 /* Cluster counts of one species, six neighbours, helical boundaries (BFS). */
-uint64_t ko_tri_cluster_counts(const uint8_t *s, uint32_t L, int species, uint64_t *counts)
+uint64_t ko_tri_cluster_counts(const uint8_t *s, uint32_t L, uint32_t H, int species, uint64_t *counts)
 {
-    uint64_t N = (uint64_t)L * L, i, nclusters = 0;
+    uint64_t N = (uint64_t)L * H, i, nclusters = 0;
     uint8_t *seen = (uint8_t *)calloc(N, 1);
     uint64_t *queue = (uint64_t *)malloc(N * sizeof(uint64_t));
     if (!seen || !queue) {
@@ -798,10 +811,10 @@ uint64_t ko_tri_cluster_counts(const uint8_t *s, uint32_t L, int species, uint64
 /* Random-neighbour similar count on the triangular lattice: site i draws   */
 /* d = (word * 6) >> 32 from word (i mod 4) of Philox block                 */
 /* (i div 4, 1, t_lo, t_hi28 | TAG_OBSERVE<<28).                             */
-uint64_t ko_tri_similar_sampled(const uint8_t *s, uint32_t L, uint64_t seed, uint64_t t)
+uint64_t ko_tri_similar_sampled(const uint8_t *s, uint32_t L, uint32_t H, uint64_t seed, uint64_t t)
 {
     uint32_t key[2], ctr[4], w[4];
-    uint64_t N = (uint64_t)L * L, i, same = 0;
+    uint64_t N = (uint64_t)L * H, i, same = 0;
     seed_to_key(seed, key);
     for (i = 0; i < N; ++i) {
         uint32_t d;
@@ -824,9 +837,9 @@ uint64_t ko_tri_similar_sampled(const uint8_t *s, uint32_t L, uint64_t seed, uin
  * uniform site, one of its six neighbours, and accepting the exchange with
  * probability min(1, exp(-omega dN_AB)), dN_AB by recounting the unlike bonds
  * of both sites before and after.  Its own xoshiro256** stream. */
-static int tri_bonds_of_pair(const uint8_t *s, uint32_t L, uint64_t a, uint64_t b)
+static int tri_bonds_of_pair(const uint8_t *s, uint32_t L, uint32_t H, uint64_t a, uint64_t b)
 {
-    uint64_t N = (uint64_t)L * L;
+    uint64_t N = (uint64_t)L * H;
     uint32_t d;
     int n = 0;
     for (d = 0; d < 6; ++d) {
@@ -840,10 +853,11 @@ static int tri_bonds_of_pair(const uint8_t *s, uint32_t L, uint64_t a, uint64_t 
     return n;
 }
 
-uint64_t ko_tri_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_seed, uint64_t n_steps)
+uint64_t ko_tri_seq_kawasaki(uint8_t *s, uint32_t L, uint32_t H, double omega, uint64_t rng_seed,
+                            uint64_t n_steps)
 {
     uint64_t st[4], sm = rng_seed, accepted = 0, step, a;
-    uint64_t N = (uint64_t)L * L;
+    uint64_t N = (uint64_t)L * H;
     int k;
     for (k = 0; k < 4; ++k)
         st[k] = splitmix64_next(&sm);
@@ -857,9 +871,9 @@ uint64_t ko_tri_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_
             int before, dU;
             if (s[c] == s[b])
                 continue;
-            before = tri_bonds_of_pair(s, L, c, b);
+            before = tri_bonds_of_pair(s, L, H, c, b);
             tmp = s[c]; s[c] = s[b]; s[b] = tmp;
-            dU = tri_bonds_of_pair(s, L, c, b) - before;
+            dU = tri_bonds_of_pair(s, L, H, c, b) - before;
             if (u < exp(-omega * (double)dU)) {
                 ++accepted;
             } else {
@@ -868,4 +882,114 @@ uint64_t ko_tri_seq_kawasaki(uint8_t *s, uint32_t L, double omega, uint64_t rng_
         }
     }
     return accepted;
+}
+
+/* ====================================================================== */
+/* The paper's literal MPKK (Materials and Methods, "Massive Parallel      */
+/* Kawasaki Kinetics", Fig. 4): the ring is covered by 7-site domains (a   */
+/* centre and its six neighbours).  With H rows of L sites, L = 3 or 5     */
+/* (mod 7) and H = 0 (mod 7), the domains centred on the sites c = k       */
+/* (mod 7) partition the ring for each k = 0..6 (the offsets 0, +-1, +-L,  */
+/* +-(L-1) meet every residue mod 7 once).  One step is 7 iterations; each */
+/* draws k uniformly, with replacement, and makes one Kawasaki attempt in  */
+/* every domain of D(k) at once: the centre picks one of its six           */
+/* neighbours.  "At once" is read as synchronous: every domain decides     */
+/* from the lattice as it stood at the start of the iteration, then all    */
+/* accepted exchanges are applied (domains are disjoint, so no two write   */
+/* one site).  Decisions that read a site an adjacent domain exchanges are */
+/* the conflicts whose bias this variant exists to measure.                */
+/* Random numbers (Philox4x32-10, key = seed), step t, iteration j:        */
+/*   k_j = (w * 7) >> 32, w = word (j mod 4) of block (j div 4, 2, t_lo,   */
+/*   t_hi28 | 8<<28);                                                       */
+/*   domain m (centre c = k_j + 7m): block (m div 2, j, t_lo,              */
+/*   t_hi28 | 9<<28), word 2(m mod 2) gives the direction d = (w*6) >> 32, */
+/*   word 2(m mod 2) + 1 the uniform U; acceptance as in ko_tri_sweeps.    */
+/* ====================================================================== */
+#define KO_TAG_MPKK_K 8u
+#define KO_TAG_MPKK 9u
+
+int ko_mpkk_k(uint64_t seed, uint64_t t, int j)
+{
+    uint32_t key[2], ctr[4], b[4];
+    seed_to_key(seed, key);
+    ctr[0] = (uint32_t)(j >> 2);
+    ctr[1] = 2u;
+    ctr[2] = (uint32_t)t;
+    ctr[3] = ctr3(t, KO_TAG_MPKK_K);
+    ko_philox4x32_10(ctr, key, b);
+    return (int)(((uint64_t)b[j & 3] * 7u) >> 32);
+}
+
+void ko_mpkk_domain_randoms(uint64_t seed, uint64_t t, int j, uint64_t m, uint32_t *dir, uint32_t *u)
+{
+    uint32_t key[2], ctr[4], b[4];
+    seed_to_key(seed, key);
+    ctr[0] = (uint32_t)(m >> 1);
+    ctr[1] = (uint32_t)j;
+    ctr[2] = (uint32_t)t;
+    ctr[3] = ctr3(t, KO_TAG_MPKK);
+    ko_philox4x32_10(ctr, key, b);
+    *dir = (uint32_t)(((uint64_t)b[2 * (m & 1u)] * 6u) >> 32);
+    *u = b[2 * (m & 1u) + 1];
+}
+
+/* One synchronous iteration over the domains of D(k) with the given
+ * directions and uniforms (one per domain, m = 0 .. N/7 - 1).  Returns the
+ * accepted exchanges; -1 on allocation failure. */
+int64_t ko_mpkk_iteration(uint8_t *s, uint32_t L, uint32_t H, int k, const uint32_t *dir, const uint32_t *u,
+                          const uint64_t T[11])
+{
+    uint64_t N = (uint64_t)L * H, m;
+    int64_t acc = 0;
+    uint8_t *old = (uint8_t *)malloc(N);
+    if (!old)
+        return -1;
+    memcpy(old, s, N);
+    for (m = 0; m < N / 7; ++m) {
+        uint64_t c = (uint64_t)k + 7 * m;
+        uint64_t b = tri_nb(c, tri_offset(L, dir[m]), N);
+        if (old[c] != old[b]) {
+            int n = tri_unlike_except(old, L, H, c, b) + tri_unlike_except(old, L, H, b, c);
+            if ((uint64_t)u[m] < T[n]) {
+                s[c] = old[b];
+                s[b] = old[c];
+                ++acc;
+            }
+        }
+    }
+    free(old);
+    return acc;
+}
+
+uint64_t ko_mpkk_steps(uint8_t *s, uint32_t L, uint32_t H, double omega, uint64_t seed, uint64_t t0,
+                       uint64_t n_steps)
+{
+    uint64_t T[11], N = (uint64_t)L * H, M = N / 7, acc = 0, t, m;
+    uint32_t *dir = (uint32_t *)malloc(M * sizeof(uint32_t));
+    uint32_t *u = (uint32_t *)malloc(M * sizeof(uint32_t));
+    int j;
+    if (!dir || !u) {
+        free(dir);
+        free(u);
+        return ~(uint64_t)0;
+    }
+    ko_tri_thresholds(omega, T);
+    for (t = t0; t < t0 + n_steps; ++t) {
+        for (j = 0; j < 7; ++j) {
+            int k = ko_mpkk_k(seed, t, j);
+            int64_t a;
+            for (m = 0; m < M; ++m)
+                ko_mpkk_domain_randoms(seed, t, j, m, &dir[m], &u[m]);
+            a = ko_mpkk_iteration(s, L, H, k, dir, u, T);
+            if (a < 0) {
+                acc = ~(uint64_t)0;
+                goto out;
+            }
+            acc += (uint64_t)a;
+        }
+    }
+out:
+    free(dir);
+    free(u);
+    return acc;
 }

@@ -165,7 +165,7 @@ namespace {
   } while (0)
 
 size_t lattice_bytes(const kk_sim* h) {
-  return h->layout == kLayoutBits ? (size_t)h->L * (size_t)(h->L / 32) * 4 : (size_t)h->L * (size_t)h->L;
+  return h->layout == kLayoutBits ? (size_t)h->H * (size_t)(h->L / 32) * 4 : (size_t)h->L * (size_t)h->H;
 }
 
 void free_all(kk_sim* h) {
@@ -195,9 +195,9 @@ kk_status dmalloc(kk_sim* h, void** p, size_t bytes) {
 // Uniform random subset of exactly n1 sites: radix select of the n1-th
 // smallest Philox key, then ties (equal 64-bit keys) broken by site index.
 kk_status place_initial(kk_sim* h) {
-  const int L = h->L;
-  const size_t N = (size_t)L * L;
-  const uint64_t n1 = place_count(L, h->composition);
+  const int L = h->L, H = h->H;
+  const size_t N = (size_t)L * H;
+  const uint64_t n1 = place_count(L, H, h->composition);
   void* dst = h->lat[h->cur];
   const size_t bytes = lattice_bytes(h);
   if (n1 == 0) {
@@ -228,7 +228,7 @@ kk_status place_initial(kk_sim* h) {
     h->poisoned = true;
     return set_error(KK_EDEVICE, "%s failed: %s", what, hipGetErrorString(e));
   };
-  hipError_t e = launch_init_keys(keys, L, h->k0, h->k1, h->stream);
+  hipError_t e = launch_init_keys(keys, L, H, h->k0, h->k1, h->stream);
   if (e != hipSuccess) return fail("init_keys", e);
   uint64_t prefix = 0, need = n1;
   for (int shift = 56; shift >= 0; shift -= 8) {
@@ -249,7 +249,7 @@ kk_status place_initial(kk_sim* h) {
   }
   // sites with key < prefix are ones; `need` of the sites with key == prefix too
   if ((e = hipMemsetAsync(eq_count, 0, sizeof(unsigned), h->stream)) != hipSuccess) return fail("memset", e);
-  if ((e = launch_init_mark(keys, L, h->layout, prefix, dst, eq_count, eq_list, eq_cap, h->stream)) != hipSuccess)
+  if ((e = launch_init_mark(keys, L, H, h->layout, prefix, dst, eq_count, eq_list, eq_cap, h->stream)) != hipSuccess)
     return fail("init_mark", e);
   unsigned neq = 0;
   if ((e = hipMemcpyAsync(&neq, eq_count, sizeof neq, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
@@ -314,7 +314,7 @@ kk_status reset_partials(kk_sim* h) {
     (void)hipFree(h->partials);
     h->partials = nullptr;
   }
-  h->npartials = h->geom ? (size_t)kTriPartials : tile_count(h->L, h->tile);
+  h->npartials = h->geom != 0 ? (size_t)kTriPartials : tile_count(h->L, h->tile);
   kk_status st = dmalloc(h, (void**)&h->partials, h->npartials * sizeof(unsigned long long));
   if (st != KK_OK) return st;
   KK_HIP(hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream));
@@ -325,8 +325,9 @@ kk_status reset_partials(kk_sim* h) {
 // Launch sweeps [h->t, h->t + n) on the handle's stream.  With `timing`, an
 // event pair brackets every launch and the kernel time is accumulated.
 kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
-  if (h->geom == 1) {
-    // triangular: 16 launches (one per class) per sweep, in place
+  if (h->geom != 0) {
+    // triangular: 16 launches (one per class) per sweep in place, or 7
+    // synchronous MPKK iterations per step between the two buffers
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
       KK_HIP(hipEventCreate(&ev[0]));
@@ -335,11 +336,20 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
     }
     if (n > 0) h->epoch += 1;
     for (uint64_t k = 0; k < n; ++k) {
-      for (int ph = 0; ph < 16; ++ph)
-        KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->k0, h->k1, h->t, ph, h->tacc,
-                                h->partials, h->stream));
+      if (h->geom == 1) {
+        for (int ph = 0; ph < 16; ++ph)
+          KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->H, h->k0, h->k1, h->t, ph,
+                                  h->tacc, h->partials, h->stream));
+      } else {
+        for (int j = 0; j < 7; ++j) {
+          KK_HIP(launch_mpkk_iteration(static_cast<const uint8_t*>(h->lat[h->cur]),
+                                       static_cast<uint8_t*>(h->lat[h->cur ^ 1]), h->L, h->H, h->k0, h->k1, h->t, j,
+                                       h->tacc, h->partials, h->stream));
+          h->cur ^= 1;
+        }
+      }
       h->t += 1;
-      h->attempts += (uint64_t)h->L * (uint64_t)h->L;
+      h->attempts += (uint64_t)h->L * (uint64_t)h->H;
     }
     if (kernel_ms) {
       KK_HIP(hipEventRecord(ev[1], h->stream));
@@ -350,7 +360,7 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
       (void)hipEventDestroy(ev[0]);
       (void)hipEventDestroy(ev[1]);
     }
-    if (launches) *launches = 16 * n;
+    if (launches) *launches = (h->geom == 1 ? 16 : 7) * n;
     return KK_OK;
   }
   SweepParams p{};
@@ -411,8 +421,8 @@ kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t 
   return KK_OK;
 }
 
-uint64_t place_count(int L, double composition) {
-  const double N = (double)L * (double)L;
+uint64_t place_count(int L, int H, double composition) {
+  const double N = (double)L * (double)H;
   double v = std::floor(composition * N + 0.5);
   if (v < 0.0) v = 0.0;
   if (v > N) v = N;
@@ -444,10 +454,26 @@ kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omeg
     if (L % 32 != 0) return set_error(KK_EINVAL, "bit-packed layout needs L %% 32 == 0 (got %u)", L);
     lay = kLayoutBits;
   } else return set_error(KK_EINVAL, "unknown layout %u", layout);
+  return create_handle(out, L, L, 0, composition, omega_kT, seed, lay, hip_stream);
+}
 
+}  // extern "C"
+
+namespace kk {
+// A handle of H rows of L sites on geometry `geom` (0 square torus; 1 triangular,
+// conflict-free classes; 2 triangular, literal MPKK), arguments already validated.
+kk_status create_handle(kk_sim** out, uint32_t L, uint32_t H, int geom, double composition, double omega_kT,
+                        uint64_t seed, int lay, void* hip_stream) {
   kk_sim* h = new (std::nothrow) kk_sim();
   if (!h) return set_error(KK_ENOMEM, "host allocation failed");
   h->L = (int)L;
+  h->H = (int)H;
+  h->geom = geom;
+  for (int n = 0; n <= 10; ++n) {
+    const double p = std::exp(-omega_kT * (double)(10 - 2 * n));
+    const double v = std::ceil(p * 4294967296.0);
+    h->tacc.T[n] = (v >= 4294967296.0) ? 4294967296ull : (uint64_t)v;
+  }
   h->layout = lay;
   h->composition = composition;
   h->omega = omega_kT;
@@ -455,7 +481,7 @@ kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omeg
   h->k0 = (uint32_t)(seed & 0xFFFFFFFFu);
   h->k1 = (uint32_t)(seed >> 32);
   acceptance_table(omega_kT, h->T, &h->acc);
-  default_tile(h->L, lay, &h->tile);
+  if (geom == 0) default_tile(h->L, lay, &h->tile);
   kk_status st = KK_OK;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) {
@@ -489,27 +515,42 @@ kk_status kk_create_ex(kk_sim** out, uint32_t L, double composition, double omeg
   return KK_OK;
 }
 
-kk_status kk_create_triangular(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed,
-                               void* hip_stream) {
+}  // namespace kk
+
+extern "C" {
+
+kk_status kk_create_triangular_ex(kk_sim** out, uint32_t L, uint32_t H, uint32_t scheme, double composition,
+                                  double omega_kT, uint64_t seed, void* hip_stream) {
   if (!out) return set_error(KK_EINVAL, "out is NULL");
   *out = nullptr;
-  if (L < 4 || L % 8 != 4 || L > 32764)
-    return set_error(KK_EINVAL, "triangular lattice needs L %% 8 == 4 in [4, 32764] (got %u)", L);
-  kk_sim* h = nullptr;
-  kk_status st = kk_create_ex(&h, L, composition, omega_kT, seed, KK_LAYOUT_INT8, hip_stream);
-  if (st != KK_OK) return st;
-  h->geom = 1;
-  for (int n = 0; n <= 10; ++n) {
-    const double p = std::exp(-omega_kT * (double)(10 - 2 * n));
-    const double v = std::ceil(p * 4294967296.0);
-    h->tacc.T[n] = (v >= 4294967296.0) ? 4294967296ull : (uint64_t)v;
+  if (!(composition >= 0.0 && composition <= 1.0))
+    return set_error(KK_EINVAL, "composition must lie in [0, 1]");
+  if (!std::isfinite(omega_kT)) return set_error(KK_EINVAL, "omega must be finite");
+  if ((uint64_t)L * H > 0xFFFFFFF0ull || L > 65535 || H > 65535)
+    return set_error(KK_EINVAL, "lattice too large (%u x %u)", L, H);
+  if (scheme == KK_TRI_CLASSES) {
+    if (L < 4 || L % 8 != 4 || H < 4 || H % 4 != 0)
+      return set_error(KK_EINVAL, "the 16-class schedule needs L %% 8 == 4 and H %% 4 == 0 (got %u x %u)", L, H);
+  } else if (scheme == KK_TRI_MPKK) {
+    if (L < 3 || (L % 7 != 3 && L % 7 != 5) || H < 7 || H % 7 != 0)
+      return set_error(KK_EINVAL, "the 7-site domain cover needs L %% 7 in {3, 5} and H %% 7 == 0 (got %u x %u)", L,
+                       H);
+  } else {
+    return set_error(KK_EINVAL, "unknown scheme %u", scheme);
   }
-  st = reset_partials(h);  // kTriPartials sums; nothing has been counted yet
-  if (st != KK_OK) {
-    kk_destroy(h);
-    return st;
-  }
-  *out = h;
+  return create_handle(out, L, H, scheme == KK_TRI_CLASSES ? 1 : 2, composition, omega_kT, seed, kLayoutInt8,
+                       hip_stream);
+}
+
+kk_status kk_create_triangular(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed,
+                               void* hip_stream) {
+  return kk_create_triangular_ex(out, L, L, KK_TRI_CLASSES, composition, omega_kT, seed, hip_stream);
+}
+
+kk_status kk_shape(kk_sim* h, uint32_t* L, uint32_t* H) {
+  KK_GUARD(h);
+  if (L) *L = (uint32_t)h->L;
+  if (H) *H = (uint32_t)h->H;
   return KK_OK;
 }
 
@@ -521,7 +562,8 @@ kk_status kk_restart(kk_sim* h, uint32_t start) {
     const kk_status st = place_initial(h);
     if (st != KK_OK) return st;
   } else {
-    KK_HIP(launch_fill_segregated(h->lat[h->cur], h->layout, h->L, place_count(h->L, h->composition), h->stream));
+    KK_HIP(launch_fill_segregated(h->lat[h->cur], h->layout, h->L, h->H, place_count(h->L, h->H, h->composition),
+                                  h->stream));
   }
   KK_HIP(hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream));
   KK_HIP(hipStreamSynchronize(h->stream));
@@ -535,7 +577,7 @@ kk_status kk_restart(kk_sim* h, uint32_t start) {
 kk_status kk_tri_thresholds(kk_sim* h, uint64_t out[11]) {
   KK_GUARD(h);
   if (!out) return set_error(KK_EINVAL, "out is NULL");
-  if (h->geom != 1) return set_error(KK_EINVAL, "square lattice: use kk_thresholds");
+  if (h->geom == 0) return set_error(KK_EINVAL, "square lattice: use kk_thresholds");
   for (int i = 0; i < 11; ++i) out[i] = h->tacc.T[i];
   return KK_OK;
 }
@@ -581,8 +623,8 @@ kk_status kk_sweep_timed(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
 kk_status kk_energy(kk_sim* h, uint64_t* n_unlike, double* energy_kT) {
   KK_GUARD(h);
   KK_HIP(hipMemsetAsync(h->counters + 1, 0, sizeof(unsigned long long), h->stream));
-  if (h->geom == 1)
-    KK_HIP(launch_tri_energy(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->counters + 1, h->stream));
+  if (h->geom != 0)
+    KK_HIP(launch_tri_energy(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->H, h->counters + 1, h->stream));
   else
     KK_HIP(launch_energy(h->lat[h->cur], h->layout, h->L, h->counters + 1, h->stream));
   unsigned long long v = 0;
@@ -598,7 +640,7 @@ kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap
   if (species != 0 && species != 1) return set_error(KK_EINVAL, "species must be 0 or 1");
   if (!n_out) return set_error(KK_EINVAL, "n_out is NULL");
   if (cap > 0 && !out) return set_error(KK_EINVAL, "out is NULL with cap > 0");
-  const size_t N = (size_t)h->L * h->L;
+  const size_t N = (size_t)h->L * h->H;
   if (!h->ccl_ready) {
     kk_status st = dmalloc(h, (void**)&h->ccl.parent, N * 4);
     if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.size, N * 4);
@@ -615,7 +657,7 @@ kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap
     KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
     KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
     KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
-    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, species, h->ccl, h->geom == 1, h->stream));
+    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, h->H, species, h->ccl, h->geom != 0, h->stream));
     std::vector<unsigned> hs(kSmallSizes);
     unsigned nbig = 0;
     KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
@@ -651,13 +693,13 @@ kk_status kk_observe(kk_sim* h, int species, kk_observables* out) {
   o.sweep = h->t;
   kk_status st = kk_energy(h, &o.n_unlike, &o.energy_kT);
   if (st != KK_OK) return st;
-  const uint64_t N = (uint64_t)h->L * (uint64_t)h->L;
+  const uint64_t N = (uint64_t)h->L * (uint64_t)h->H;
   // the lattice has 2N bonds (square) or 3N (triangular)
-  o.similar_exact = 1.0 - (double)o.n_unlike / (double)((h->geom == 1 ? 3 : 2) * N);
+  o.similar_exact = 1.0 - (double)o.n_unlike / (double)((h->geom != 0 ? 3 : 2) * N);
   KK_HIP(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
-  if (h->geom == 1)
-    KK_HIP(launch_tri_similar(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->k0, h->k1, h->t, h->counters,
-                              h->stream));
+  if (h->geom != 0)
+    KK_HIP(launch_tri_similar(static_cast<const uint8_t*>(h->lat[h->cur]), h->L, h->H, h->k0, h->k1, h->t,
+                              h->counters, h->stream));
   else
     KK_HIP(launch_similar_sampled(h->lat[h->cur], h->layout, h->L, h->k0, h->k1, h->t, h->counters, h->stream));
   unsigned long long same = 0;
@@ -696,8 +738,8 @@ kk_status kk_sweep_series(kk_sim* h, uint64_t every, uint64_t count, int species
 
 kk_status kk_get_lattice(kk_sim* h, uint8_t* host_out, size_t n) {
   KK_GUARD(h);
-  const size_t N = (size_t)h->L * h->L;
-  if (!host_out || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*L = %zu bytes", N);
+  const size_t N = (size_t)h->L * h->H;
+  if (!host_out || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*H = %zu bytes", N);
   if (h->layout == kLayoutInt8) {
     KK_HIP(hipMemcpyAsync(host_out, h->lat[h->cur], N, hipMemcpyDeviceToHost, h->stream));
     KK_HIP(hipStreamSynchronize(h->stream));
@@ -719,8 +761,8 @@ kk_status kk_get_lattice(kk_sim* h, uint8_t* host_out, size_t n) {
 
 kk_status kk_set_lattice(kk_sim* h, const uint8_t* host_in, size_t n, uint64_t sweep_t) {
   KK_GUARD(h);
-  const size_t N = (size_t)h->L * h->L;
-  if (!host_in || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*L = %zu bytes", N);
+  const size_t N = (size_t)h->L * h->H;
+  if (!host_in || n != N) return set_error(KK_EINVAL, "need a buffer of exactly L*H = %zu bytes", N);
   for (size_t i = 0; i < N; ++i)
     if (host_in[i] > 1) return set_error(KK_EINVAL, "site %zu holds %u; sites must be 0 or 1", i, host_in[i]);
   if (sweep_t >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "sweep counter must be < 2^60");
@@ -759,7 +801,7 @@ kk_status kk_stats(kk_sim* h, uint64_t* sweeps, uint64_t* attempts, uint64_t* ac
 kk_status kk_thresholds(kk_sim* h, uint64_t out[7]) {
   KK_GUARD(h);
   if (!out) return set_error(KK_EINVAL, "out is NULL");
-  if (h->geom == 1) return set_error(KK_EINVAL, "triangular lattice: use kk_tri_thresholds (11 entries)");
+  if (h->geom != 0) return set_error(KK_EINVAL, "triangular lattice: use kk_tri_thresholds (11 entries)");
   for (int i = 0; i < 7; ++i) out[i] = h->T[i];
   return KK_OK;
 }
@@ -773,7 +815,7 @@ kk_status kk_info(kk_sim* h, uint32_t* L, uint32_t* layout) {
 
 kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread) {
   KK_GUARD(h);
-  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
+  if (h->geom != 0) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   TileConfig tc{};
   tc.ku = (int)units_per_thread;
   if (tile_words == 0) {
@@ -794,7 +836,7 @@ kk_status kk_set_tile(kk_sim* h, uint32_t tile_words, uint32_t tile_rows, uint32
 kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, uint32_t* tile_rows,
                       uint32_t* units_per_thread, double* us_per_sweep) {
   KK_GUARD(h);
-  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
+  if (h->geom != 0) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   if (trial_sweeps == 0) trial_sweeps = 20;
   if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
   const int L = h->L;
@@ -890,7 +932,7 @@ kk_status kk_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* tile_words, ui
 
 kk_status kk_get_tile(kk_sim* h, uint32_t* tile_words, uint32_t* tile_rows, uint32_t* units_per_thread) {
   KK_GUARD(h);
-  if (h->geom == 1) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
+  if (h->geom != 0) return set_error(KK_EINVAL, "the triangular lattice has no sweep tiles");
   if (tile_words) *tile_words = h->tile.cyclic ? 0u : (uint32_t)h->tile.tww;
   if (tile_rows) *tile_rows = (uint32_t)h->tile.th;
   if (units_per_thread) *units_per_thread = (uint32_t)h->tile.ku;

@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void similar_sampled(const void* lat, int layo
 // words 0 and 1; the n1 sites with the smallest (key, index) get type 1.
 // The n1-th smallest key is found by an 8-pass MSB-first radix select.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1) {
-  const size_t n = (size_t)L * L;
+__global__ __launch_bounds__(256) void init_keys(uint64_t* keys, int L, int H, uint32_t k0, uint32_t k1) {
+  const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const uint32_t y = (uint32_t)(i / L), x = (uint32_t)(i - (size_t)y * L);
     const Philox4 r = philox10(y, x, 0u, kTagInit << 28, k0, k1);
@@ -106,11 +106,11 @@ __global__ __launch_bounds__(256) void radix_hist(const uint64_t* keys, size_t n
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat,
+__global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, int H, int layout, uint64_t kth, void* lat,
                                                  unsigned* eq_count, uint32_t* eq_list, unsigned eq_cap) {
   if (layout == kLayoutBits) {
     const int wpr = L >> 5;
-    const size_t nw = (size_t)L * wpr;
+    const size_t nw = (size_t)H * wpr;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
       uint32_t v = 0;
       const size_t base = i * 32;  // words tile rows exactly, so site index = 32 * word + bit
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, in
       static_cast<uint32_t*>(lat)[i] = v;
     }
   } else {
-    const size_t n = (size_t)L * L;
+    const size_t n = (size_t)L * H;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
       const uint64_t k = keys[i];
       uint8_t v = 0;
@@ -189,8 +189,8 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
   }
 }
 
-__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int species, uint32_t* parent) {
-  const size_t n = (size_t)L * L;
+__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species, uint32_t* parent) {
+  const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
     parent[i] = (site_bit(lat, layout, L, x, y) == species) ? (uint32_t)i : kNone;
@@ -212,8 +212,8 @@ __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, in
 // Segregated start: the first n1 sites in index order i = y*L + x hold type 1
 // (full rows 0 .. n1/L - 1 and the start of the next one).  Bit-packed words
 // tile rows exactly, so word w holds sites 32w .. 32w + 31.
-__global__ __launch_bounds__(256) void fill_segregated(void* lat, int layout, int L, uint64_t n1) {
-  const size_t n = (size_t)L * L;
+__global__ __launch_bounds__(256) void fill_segregated(void* lat, int layout, int L, int H, uint64_t n1) {
+  const size_t n = (size_t)L * H;
   if (layout == kLayoutBits) {
     uint32_t* w = static_cast<uint32_t*>(lat);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n / 32; i += (size_t)gridDim.x * blockDim.x) {
@@ -227,11 +227,11 @@ __global__ __launch_bounds__(256) void fill_segregated(void* lat, int layout, in
   }
 }
 
-// Triangular lattice, helical boundaries (sites i = y*L + x on one ring of N):
+// Triangular lattice, helical boundaries (H rows of L sites, i = y*L + x on one ring of N = L*H):
 // unite i with i+1, i+L and i+L-1 (mod N) when both are of the species; the
 // other three of the six bonds are forward bonds of the neighbours.
-__global__ __launch_bounds__(256) void ccl_merge_tri(const uint8_t* lat, int L, int species, uint32_t* parent) {
-  const uint32_t N = (uint32_t)L * (uint32_t)L;
+__global__ __launch_bounds__(256) void ccl_merge_tri(const uint8_t* lat, int L, int H, int species, uint32_t* parent) {
+  const uint32_t N = (uint32_t)L * (uint32_t)H;
   const uint32_t off[3] = {1u, (uint32_t)L, (uint32_t)L - 1u};
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     if (lat[i] != species) continue;
@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void ccl_merge_tri(const uint8_t* lat, int L, 
 }
 
 // After all unions: point every site straight at its root.
-__global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L) {
-  const size_t n = (size_t)L * L;
+__global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L, int H) {
+  const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     if (ld_parent(parent, (uint32_t)i) == kNone) continue;
     const uint32_t r = find_root_halving(parent, (uint32_t)i);
@@ -257,8 +257,8 @@ __global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L) {
 // Cluster sizes (parents flattened): one add per site onto its root, aggregated over the
 // wavefront first (lanes with the same root add once, by their lowest lane),
 // so a spanning cluster costs one atomic per wave instead of one per site.
-__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, uint32_t* size) {
-  const size_t n = (size_t)L * L;
+__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, int H, uint32_t* size) {
+  const size_t n = (size_t)L * H;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const int lane = (int)__lane_id();
   // the loop bound is uniform over the block, so every lane joins every ballot
@@ -278,12 +278,12 @@ __global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, uint32
   }
 }
 
-__global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, unsigned* hist, uint32_t* big,
+__global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, int H, unsigned* hist, uint32_t* big,
                                                 unsigned* big_count, unsigned big_cap) {
   __shared__ unsigned h[kSmallSizes];
   for (int k = threadIdx.x; k < kSmallSizes; k += blockDim.x) h[k] = 0;
   __syncthreads();
-  const size_t n = (size_t)L * L;
+  const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const uint32_t s = size[i];
     if (s == 0) continue;
@@ -342,8 +342,8 @@ hipError_t launch_similar_sampled(const void* lat, int layout, int L, uint32_t k
   return hipGetLastError();
 }
 
-hipError_t launch_init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1, hipStream_t stream) {
-  hipLaunchKernelGGL(init_keys, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream, keys, L, k0, k1);
+hipError_t launch_init_keys(uint64_t* keys, int L, int H, uint32_t k0, uint32_t k1, hipStream_t stream) {
+  hipLaunchKernelGGL(init_keys, dim3(grid_for((size_t)L * H, 256)), dim3(256), 0, stream, keys, L, H, k0, k1);
   return hipGetLastError();
 }
 
@@ -353,10 +353,10 @@ hipError_t launch_radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, in
   return hipGetLastError();
 }
 
-hipError_t launch_init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat, unsigned* eq_count,
+hipError_t launch_init_mark(const uint64_t* keys, int L, int H, int layout, uint64_t kth, void* lat, unsigned* eq_count,
                             uint32_t* eq_list, unsigned eq_cap, hipStream_t stream) {
-  const size_t n = layout == kLayoutBits ? (size_t)L * (L >> 5) : (size_t)L * L;
-  hipLaunchKernelGGL(init_mark, dim3(grid_for(n, 256)), dim3(256), 0, stream, keys, L, layout, kth, lat, eq_count,
+  const size_t n = layout == kLayoutBits ? (size_t)H * (L >> 5) : (size_t)L * H;
+  hipLaunchKernelGGL(init_mark, dim3(grid_for(n, 256)), dim3(256), 0, stream, keys, L, H, layout, kth, lat, eq_count,
                      eq_list, eq_cap);
   return hipGetLastError();
 }
@@ -367,20 +367,21 @@ hipError_t launch_set_sites(const uint32_t* idx, unsigned n, int L, int layout, 
   return hipGetLastError();
 }
 
-hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, bool triangular,
+hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, const CclBuffers& b, bool triangular,
                       hipStream_t stream) {
-  const size_t n = (size_t)L * L;
+  const size_t n = (size_t)L * H;
   const int g = grid_for(n, 256);
-  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
+  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, H, species, b.parent);
   if (triangular) {
-    hipLaunchKernelGGL(ccl_merge_tri, dim3(g), dim3(256), 0, stream, static_cast<const uint8_t*>(lat), L, species,
+    hipLaunchKernelGGL(ccl_merge_tri, dim3(g), dim3(256), 0, stream, static_cast<const uint8_t*>(lat), L, H, species,
                        b.parent);
   } else {
+    // the square torus: H == L
     hipLaunchKernelGGL(ccl_merge, dim3(g), dim3(256), 0, stream, lat, layout, L, species, b.parent);
   }
-  hipLaunchKernelGGL(ccl_flatten, dim3(g), dim3(256), 0, stream, b.parent, L);
-  hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, b.size);
-  hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, b.hist, b.big,
+  hipLaunchKernelGGL(ccl_flatten, dim3(g), dim3(256), 0, stream, b.parent, L, H);
+  hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, H, b.size);
+  hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, H, b.hist, b.big,
                      b.big_count, b.big_cap);
   return hipGetLastError();
 }
@@ -395,8 +396,9 @@ hipError_t launch_unpack(const uint32_t* in, uint8_t* out, int L, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_fill_segregated(void* lat, int layout, int L, uint64_t n1, hipStream_t stream) {
-  hipLaunchKernelGGL(fill_segregated, dim3(grid_for((size_t)L * L, 256)), dim3(256), 0, stream, lat, layout, L, n1);
+hipError_t launch_fill_segregated(void* lat, int layout, int L, int H, uint64_t n1, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_segregated, dim3(grid_for((size_t)L * H, 256)), dim3(256), 0, stream, lat, layout, L, H,
+                     n1);
   return hipGetLastError();
 }
 

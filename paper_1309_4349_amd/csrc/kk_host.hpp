@@ -20,7 +20,7 @@ struct TileConfig {
 
 kk_status set_error(kk_status st, const char* fmt, ...);
 void acceptance_table(double omega, uint64_t T[7], Accept* acc);
-uint64_t place_count(int L, double composition);
+uint64_t place_count(int L, int H, double composition);
 int max_threads(int ku);
 bool cyclic_fits(int L);
 void default_tile(int L, int layout, TileConfig* tc);
@@ -31,7 +31,8 @@ bool tile_valid(int L, const TileConfig& tc, std::string* why);
 
 // A simulation handle (the opaque kk_sim of kk.h).
 struct kk_sim {
-  int L = 0;
+  int L = 0;                             // sites per row
+  int H = 0;                             // rows (H == L on the square torus)
   int layout = 0;
   double composition = 0, omega = 0;
   uint64_t seed = 0;
@@ -52,7 +53,8 @@ struct kk_sim {
   kk::TileConfig tile{};
   kk::CclBuffers ccl{};
   bool ccl_ready = false;
-  int geom = 0;                          // 0: square torus; 1: triangular, helical (int8 ring)
+  int geom = 0;                          // 0 square torus; triangular helical int8 ring: 1 with the
+                                         // conflict-free 16 classes, 2 with the literal MPKK cover
   kk::TriAccept tacc{};                  // triangular thresholds
   uint64_t epoch = 0;                    // bumped whenever the lattice may change
   uint64_t hist_epoch = ~(uint64_t)0;    // epoch and species of the cached histogram
@@ -68,6 +70,8 @@ kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t 
 
 // batch engine over borrowed handles (kk_batch.cpp), used by the job server:
 // the batch never destroys these sims; replan after the set changes.
+kk_status create_handle(kk_sim** out, uint32_t L, uint32_t H, int geom, double composition, double omega_kT,
+                        uint64_t seed, int lay, void* hip_stream);
 kk_status batch_over(const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps, void* hip_stream,
                      kk_batch** out);
 kk_status batch_replan(kk_batch* b, const std::vector<kk_sim*>& sims, const std::vector<uint64_t>& sweeps);

@@ -72,10 +72,10 @@ hipError_t launch_similar_sampled(const void* lat, int layout, int L, uint32_t k
                                  unsigned long long* out, hipStream_t stream);
 
 // Initial placement.
-hipError_t launch_init_keys(uint64_t* keys, int L, uint32_t k0, uint32_t k1, hipStream_t stream);
+hipError_t launch_init_keys(uint64_t* keys, int L, int H, uint32_t k0, uint32_t k1, hipStream_t stream);
 hipError_t launch_radix_hist(const uint64_t* keys, size_t n, uint64_t prefix, int shift, unsigned* hist256,
                              hipStream_t stream);
-hipError_t launch_init_mark(const uint64_t* keys, int L, int layout, uint64_t kth, void* lat, unsigned* eq_count,
+hipError_t launch_init_mark(const uint64_t* keys, int L, int H, int layout, uint64_t kth, void* lat, unsigned* eq_count,
                             uint32_t* eq_list, unsigned eq_cap, hipStream_t stream);
 hipError_t launch_set_sites(const uint32_t* idx, unsigned n, int L, int layout, void* lat, hipStream_t stream);
 
@@ -90,22 +90,26 @@ struct CclBuffers {
 };
 constexpr int kSmallSizes = 4096;
 // triangular: six neighbours under helical boundaries (the int8 ring of kk_tri.hip).
-hipError_t launch_ccl(const void* lat, int layout, int L, int species, const CclBuffers& b, bool triangular,
+hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, const CclBuffers& b, bool triangular,
                       hipStream_t stream);
 
-// Triangular lattice, helical boundaries (kk_tri.hip): one launch per phase.
+// Triangular lattice, helical boundaries (kk_tri.hip): H rows of L sites on
+// one ring of N = L*H.  Conflict-free classes: one launch per phase.  The
+// literal MPKK variant: one launch per iteration, ping-pong buffers.
 constexpr int kTriPartials = 64;  // accepted-move sums, indexed by workgroup % kTriPartials
 struct TriAccept {
-  uint64_t T[11];  // T[n] = min(2^32, ceil(exp(-omega (10 - 2n)) 2^32))
+  uint64_t T[11];  // U < T[n] accepts, n = unlike neighbours of the pair (each excluding the other)
 };
-hipError_t launch_tri_phase(uint8_t* lat, int L, uint32_t k0, uint32_t k1, uint64_t t, int p, const TriAccept& acc,
-                            unsigned long long* partials, hipStream_t stream);
-hipError_t launch_tri_energy(const uint8_t* lat, int L, unsigned long long* out, hipStream_t stream);
-hipError_t launch_tri_similar(const uint8_t* lat, int L, uint32_t k0, uint32_t k1, uint64_t t,
+hipError_t launch_tri_phase(uint8_t* lat, int L, int H, uint32_t k0, uint32_t k1, uint64_t t, int p,
+                            const TriAccept& acc, unsigned long long* partials, hipStream_t stream);
+hipError_t launch_mpkk_iteration(const uint8_t* in, uint8_t* out, int L, int H, uint32_t k0, uint32_t k1, uint64_t t,
+                                 int j, const TriAccept& acc, unsigned long long* partials, hipStream_t stream);
+hipError_t launch_tri_energy(const uint8_t* lat, int L, int H, unsigned long long* out, hipStream_t stream);
+hipError_t launch_tri_similar(const uint8_t* lat, int L, int H, uint32_t k0, uint32_t k1, uint64_t t,
                               unsigned long long* out, hipStream_t stream);
 
 // Segregated start: sites 0 .. n1-1 (index y*L + x) set to 1, the rest 0.
-hipError_t launch_fill_segregated(void* lat, int layout, int L, uint64_t n1, hipStream_t stream);
+hipError_t launch_fill_segregated(void* lat, int layout, int L, int H, uint64_t n1, hipStream_t stream);
 
 // int8 <-> bit-packed conversion on the device (bit-packed needs L % 32 == 0).
 hipError_t launch_pack(const uint8_t* in, uint32_t* out, int L, hipStream_t stream);

@@ -19,11 +19,15 @@ KK_OK, KK_EINVAL, KK_ENOMEM, KK_EDEVICE, KK_ESTATE, KK_ETRUNC = range(6)
 LAYOUT_AUTO, LAYOUT_INT8, LAYOUT_BITPACKED = 0, 1, 2
 _LAYOUTS = {"auto": LAYOUT_AUTO, "int8": LAYOUT_INT8, "bitpacked": LAYOUT_BITPACKED}
 START_RANDOM, START_SEGREGATED = 0, 1
+TRI_CLASSES, TRI_MPKK = 0, 1
+_SCHEMES = {"classes": TRI_CLASSES, "mpkk": TRI_MPKK}
 _STARTS = {"random": START_RANDOM, "segregated": START_SEGREGATED}
 
 EXPORTS = [
-    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_tri_thresholds", "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
-    "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info", "kk_set_tile", "kk_get_tile", "kk_autotune",
+    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds",
+    "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
+    "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info",
+    "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
@@ -105,6 +109,8 @@ def load(path: str = LIB_PATH):
         "kk_create": [PP, U32, D, D, U64],
         "kk_create_ex": [PP, U32, D, D, U64, U32, P],
         "kk_create_triangular": [PP, U32, D, D, U64, P],
+        "kk_create_triangular_ex": [PP, U32, U32, U32, D, D, U64, P],
+        "kk_shape": [P, u32p, u32p],
         "kk_tri_thresholds": [P, u64p],
         "kk_geometry": [P, u32p],
         "kk_restart": [P, U32],
@@ -165,10 +171,14 @@ class Sim:
     """One lattice simulation owned by libkk (device memory and stream).
 
     geometry "square": the L x L torus (L % 4 == 0); "triangular": the paper's
-    six-neighbour lattice with helical boundaries (L % 8 == 4, int8 layout)."""
+    six-neighbour lattice with helical boundaries, `rows` rows of L sites
+    (default L), int8, swept by scheme "classes" (the conflict-free 16-class
+    schedule: L % 8 == 4, rows % 4 == 0) or "mpkk" (the paper's literal
+    7-domain MPKK, a comparison variant: L % 7 in {3, 5}, rows % 7 == 0)."""
 
     def __init__(self, L: int, composition: float, omega: float, seed: int, layout: str = "auto",
-                 stream: Optional[int] = None, geometry: str = "square"):
+                 stream: Optional[int] = None, geometry: str = "square", rows: Optional[int] = None,
+                 scheme: str = "classes"):
         lib = load()
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(stream) if stream else None
@@ -178,12 +188,13 @@ class Sim:
         elif geometry == "triangular":
             if layout not in ("auto", "int8"):
                 raise ValueError("the triangular lattice is stored one byte per site")
-            _check(lib.kk_create_triangular(ctypes.byref(h), L, float(composition), float(omega),
-                                            seed & (2**64 - 1), st))
+            _check(lib.kk_create_triangular_ex(ctypes.byref(h), L, rows or L, _SCHEMES[scheme], float(composition),
+                                               float(omega), seed & (2**64 - 1), st))
         else:
             raise ValueError(f"unknown geometry {geometry!r}")
         self.geometry = geometry
         self._h = h
+        self.H = (rows or L) if geometry == "triangular" else L
         self.L = L
         self.omega = float(omega)
         self.seed = seed
@@ -252,14 +263,14 @@ class Sim:
         return [buf[i].as_dict() for i in range(count)]
 
     def get_lattice(self) -> np.ndarray:
-        out = np.empty((self.L, self.L), dtype=np.uint8)
+        out = np.empty((self.H, self.L), dtype=np.uint8)
         _check(load().kk_get_lattice(self._h, out.ctypes.data, out.size))
         return out
 
     def set_lattice(self, s: np.ndarray, sweep_t: int = 0):
         s = np.ascontiguousarray(s, dtype=np.uint8)
-        if s.shape != (self.L, self.L):
-            raise ValueError(f"lattice must be {self.L}x{self.L}")
+        if s.shape != (self.H, self.L):
+            raise ValueError(f"lattice must be {self.H} rows of {self.L}")
         _check(load().kk_set_lattice(self._h, s.ctypes.data, s.size, sweep_t))
 
     def stats(self) -> Tuple[int, int, int]:

@@ -11,12 +11,12 @@ import pytest
 OFFS = lambda L: (1, -1, L, -L, L - 1, -(L - 1))  # noqa: E731  (d = 0..5)
 
 
-def nb(i, d, L):
-    return (i + OFFS(L)[d]) % (L * L)
+def nb(i, d, L, H=None):
+    return (i + OFFS(L)[d]) % (L * (H or L))
 
 
 def np_energy(s):
-    L = s.shape[0]
+    L = s.shape[1]
     f = s.ravel()
     return int(sum(np.count_nonzero(f != np.roll(f, -k)) for k in (1, L, L - 1)))
 
@@ -25,38 +25,44 @@ def test_energy_matches_a_rolled_recount(orc):
     for L, x, seed in ((4, 0.5, 1), (12, 0.3, 2), (20, 0.5, 3), (28, 0.7, 4)):
         s = orc.init(L, x, seed)
         assert orc.tri_energy(s) == np_energy(s)
+    for L, H in ((12, 8), (10, 7), (5, 14)):
+        s = orc.init_rect(L, H, 0.4, L + H)
+        assert s.shape == (H, L) and int(s.sum()) == orc.n_ones_rect(L, H, 0.4)
+        assert orc.tri_energy(s) == np_energy(s)
     z = np.zeros((12, 12), np.uint8)
     assert orc.tri_energy(z) == 0
     z[5, 5] = 1                       # one isolated site: all 6 bonds unlike
     assert orc.tri_energy(z) == 6
 
 
-def _conflicts(L):
-    N = L * L
+def _conflicts(L, H=None):
+    H = H or L
+    N = L * H
     hits = 0
     for c in range(16):
         centres = list(range(c, N, 16))
         for i1, i2 in combinations(centres, 2):
             for d1 in range(6):
-                w1 = {i1, nb(i1, d1, L)}
+                w1 = {i1, nb(i1, d1, L, H)}
                 for d2 in range(6):
-                    b2 = nb(i2, d2, L)
-                    r2 = {i2, b2} | {nb(i2, d, L) for d in range(6)} | {nb(b2, d, L) for d in range(6)}
+                    b2 = nb(i2, d2, L, H)
+                    r2 = {i2, b2} | {nb(i2, d, L, H) for d in range(6)} | {nb(b2, d, L, H) for d in range(6)}
                     w2 = {i2, b2}
-                    b1 = nb(i1, d1, L)
-                    r1 = w1 | {nb(i1, d, L) for d in range(6)} | {nb(b1, d, L) for d in range(6)}
+                    b1 = nb(i1, d1, L, H)
+                    r1 = w1 | {nb(i1, d, L, H) for d in range(6)} | {nb(b1, d, L, H) for d in range(6)}
                     hits += bool(w1 & r2) or bool(w2 & r1)
     return hits
 
 
-@pytest.mark.parametrize("L", [12, 20])
-def test_classes_are_conflict_free_for_L_4_mod_8(L):
-    assert _conflicts(L) == 0
+@pytest.mark.parametrize("L,H", [(12, 12), (20, 20), (12, 8), (20, 4), (4, 12)])
+def test_classes_are_conflict_free_for_L_4_mod_8(L, H):
+    assert _conflicts(L, H) == 0
 
 
-def test_classes_conflict_when_L_is_0_mod_8():
-    # the negative control: the pin has teeth
-    assert _conflicts(8) > 0
+@pytest.mark.parametrize("L,H", [(8, 8), (12, 6)])
+def test_classes_conflict_for_other_sizes(L, H):
+    # the negative controls: the pin has teeth
+    assert _conflicts(L, H) > 0
 
 
 def test_local_dnab_matches_a_full_recount(orc):
@@ -161,8 +167,8 @@ def test_zero_omega_mixes_to_the_random_subset_mean(orc):
 
 
 def _bfs_hist(s, species):
-    L = s.shape[0]
-    N = L * L
+    H, L = s.shape
+    N = L * H
     f = s.ravel()
     seen = np.zeros(N, bool)
     sizes = {}
@@ -175,7 +181,7 @@ def _bfs_hist(s, species):
             c = stack.pop()
             n += 1
             for d in range(6):
-                j = nb(c, d, L)
+                j = nb(c, d, L, H)
                 if f[j] == species and not seen[j]:
                     seen[j] = True
                     stack.append(j)
@@ -187,6 +193,10 @@ def test_clusters_match_a_python_bfs(orc):
     for L, x, seed in ((12, 0.4, 1), (20, 0.55, 2), (28, 0.3, 3)):
         s = orc.init(L, x, seed)
         orc.tri_sweeps(s, 1.0, seed, 0, 5)
+        for sp in (0, 1):
+            assert orc.tri_cluster_hist(s, sp) == _bfs_hist(s, sp)
+    for L, H in ((12, 8), (10, 7)):
+        s = orc.init_rect(L, H, 0.5, 9)
         for sp in (0, 1):
             assert orc.tri_cluster_hist(s, sp) == _bfs_hist(s, sp)
 
