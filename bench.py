@@ -16,7 +16,11 @@ histogram of species 1.  The line also carries:
     server replaying the Poisson job trace, saturated and below saturation;
   * triangular -- the paper's own six-neighbour helical lattice (4092^2,
     int8): attempts/s, the phase kernel's time per launch and its roofline,
-    with the triangular CPU oracle timed beside it.
+    with the triangular CPU oracle timed beside it;
+  * mpkk -- the paper's literal MPKK (7-site domain cover, synchronous
+    iterations) on a 4098 x 4095 ring: attempts/s, roofline, oracle; and its
+    bias: the equilibrium unlike-bond fraction against the exact conflict-free
+    chain on a 404 x 420 ring.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -154,6 +158,84 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
     return out
 
 
+# One literal-MPKK attempt: one Philox block per two domains (20), k draw
+# amortised (0), direction and uniform (3), 12 neighbour indices (24), 12
+# unlike tests and their sum (24), threshold (3), the 7-site domain copy with
+# the swap folded in (6 indices + 7 selects = 13) -> 87.
+MPKK_OPS_PER_ATTEMPT = 87.0
+
+
+def mpkk(steps: int, bias_steps: int, cpu: bool):
+    """Throughput of the literal MPKK and its bias against the exact chain."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1309_4349_amd import kk
+
+    L, H, x, w, seed = 4098, 4095, 0.5, 0.88, 0x13094349
+    N = L * H
+    sim = kk.Sim(L, x, w, seed, geometry="triangular", rows=H, scheme="mpkk")
+    sim.sweep(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = steps * N / dt
+    ms, launches = sim.sweep_timed(50)
+    per_launch_s = ms / 1e3 / launches
+    per_launch = N * 50 / launches
+    ops = MPKK_OPS_PER_ATTEMPT * per_launch / per_launch_s / 1e9
+    hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
+    sim.close()
+    out = {"workload": f"literal MPKK, triangular helical {L}x{H} int8, x={x}, omega={w}, {steps} steps",
+           "value": rate, "unit": "attempts/s",
+           "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
+                        "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
+                        "traffic": None, "kernel": "mpkk_iter", "kernel_us": round(per_launch_s * 1e6, 3),
+                        "launches": int(launches), "ops_per_attempt": MPKK_OPS_PER_ATTEMPT,
+                        "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
+    log(f"[bench] mpkk {L}x{H}: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
+    if cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        s = oracle.init_rect(L, H, x, seed)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < 6.0:
+            oracle.mpkk_steps(s, w, seed, n, 1)
+            n += 1
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * N / dtc, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n} steps of the same {L}x{H} ring ({dtc:.1f} s, single-threaded)"}
+        log(f"[bench] mpkk oracle {n * N / dtc:.3e} attempts/s")
+    # bias: equilibrium N_AB / 3N, 404 x 420 ring, both schemes from the same start
+    bias = []
+    L, H = 404, 420
+    N = L * H
+    for omega in (0.3, 0.5):
+        row = {"omega": omega}
+        for scheme in ("classes", "mpkk"):
+            sim = kk.Sim(L, 0.5, omega, 11, geometry="triangular", rows=H, scheme=scheme)
+            sim.sweep(3000)
+            v = []
+            for _ in range(bias_steps // 25):
+                sim.sweep(25)
+                v.append(sim.energy()[0] / (3 * N))
+            sim.close()
+            b = np.array(v[: len(v) // 20 * 20]).reshape(20, -1).mean(1)
+            row[scheme] = {"f_unlike": float(b.mean()), "stderr": float(b.std(ddof=1) / math.sqrt(20))}
+        row["mpkk_minus_exact"] = row["mpkk"]["f_unlike"] - row["classes"]["f_unlike"]
+        row["sigma"] = row["mpkk_minus_exact"] / math.hypot(row["mpkk"]["stderr"], row["classes"]["stderr"])
+        log(f"[bench] mpkk bias at omega={omega}: {row['mpkk_minus_exact']:+.5f} ({row['sigma']:.1f} sigma)")
+        bias.append(row)
+    out["bias"] = {"workload": f"{L}x{H} ring, x=0.5, 3000 burn-in + {bias_steps} measured steps each, "
+                               "20 batch means", "rows": bias}
+    return out
+
+
 def batched_vs_plain(sweeps: int, plain_sweeps: int):
     """Aggregate attempts/s of the 256-replica table: one batch run against the
     same replicas advanced one after another through the plain path."""
@@ -285,6 +367,9 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
     ap.add_argument("--no-tri", action="store_true", help="skip the triangular-lattice measurement")
     ap.add_argument("--tri-sweeps", type=int, default=500, help="sweeps of the 4092^2 triangular lattice")
+    ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
+    ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
+    ap.add_argument("--mpkk-bias-steps", type=int, default=10000, help="measured steps per bias run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -387,6 +472,10 @@ def main():
     if not args.no_tri:
         tri = triangular(args.tri_sweeps, 100, not args.no_cpu)
 
+    mp = None
+    if not args.no_mpkk:
+        mp = mpkk(args.mpkk_steps, args.mpkk_bias_steps, not args.no_cpu)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
@@ -415,6 +504,8 @@ def main():
         line["serving"] = served
     if tri is not None:
         line["triangular"] = tri
+    if mp is not None:
+        line["mpkk"] = mp
     print(json.dumps(line), flush=True)
 
 
