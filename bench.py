@@ -101,12 +101,12 @@ def cpu_baseline(job, budget_s: float = 12.0):
                       f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})"}
 
 
-# Algorithmic cost of one attempt of the triangular phase kernel, in 32-bit VALU
+# Algorithmic cost of one attempt on the triangular lattice, in 32-bit VALU
 # lane-ops: one Philox4x32-10 block per centre (40, as above), the partner
-# direction and uniform (3), 12 neighbour indices on the ring (2 each, 24),
-# 12 unlike tests and their sum (24), the threshold lookup and compare (3),
-# the swap (2) -> 96.  Algorithmic bytes: each site read and written once per
-# sweep (2 B); the neighbour reads of the 16 phases hit the caches.
+# direction and uniform (3), 12 neighbour addresses (2 each, 24), 12 unlike
+# tests and their sum (24), the threshold lookup and compare (3), the swap
+# (2) -> 96.  Algorithmic bytes: each site read and written once per sweep
+# (2 B).  The whole-sweep tile kernel recomputes a halo on top of this.
 TRI_OPS_PER_ATTEMPT = 96.0
 
 
@@ -127,6 +127,7 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rate = sweeps * N / dt
+    sim_tile = sim.tri_get_tile()
     ms, launches = sim.sweep_timed(profile_sweeps)
     per_launch_s = ms / 1e3 / launches
     per_launch = N * profile_sweeps / launches
@@ -138,8 +139,9 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
            "value": rate, "unit": "attempts/s", "n_unlike_over_3N": nab / (3 * N),
            "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
                         "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
-                        "traffic": None, "kernel": "tri_phase", "kernel_us": round(per_launch_s * 1e6, 3),
+                        "traffic": None, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase", "kernel_us": round(per_launch_s * 1e6, 3),
                         "launches": int(launches), "ops_per_attempt": TRI_OPS_PER_ATTEMPT,
+                        "tile": {"cols": sim_tile[0], "rows": sim_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
     log(f"[bench] triangular {L}^2: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
     if cpu:

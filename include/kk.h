@@ -129,11 +129,26 @@ enum {
  *   together (the domains are disjoint): the paper's simultaneous update,
  *   whose decisions may read sites that a neighbouring domain exchanges.  N
  *   attempts per step.
- * Both need N <= 2^32 - 16 and L, H <= 65535.  Energy, clusters,
+ * Both need N <= 2^31 - 1 and L, H <= 65535.  Energy, clusters,
  * observables, lattice copies, restart and stats work as for
  * kk_create_triangular; kk_get_lattice/kk_set_lattice take N = L*H bytes. */
 kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t scheme, double composition,
                                   double omega_kT, uint64_t seed, void *hip_stream);
+
+/* Whole-sweep tiles of the triangular class schedule: with cols > 0 every sweep
+ * is one launch whose workgroups each own a cols x rows tile and run all 16
+ * classes on an LDS window of the ring around it (33 more sites on every
+ * side, recomputed by each tile), writing the tile to the other lattice
+ * buffer; cols == 0 selects one launch per class, in place.  Results do not
+ * depend on the choice (the window carries every exchange that can reach the
+ * tile within a sweep).  Needs cols, rows >= 16, cols + 66 <= L, rows + 66 <= H
+ * and a window of at most 159 KiB ((cols + 66, rounded up to an odd number of
+ * 4-byte words) x (rows + 66) bytes); KK_EINVAL otherwise and for other
+ * schemes.  The default is the square tile (320, 256, 192, 160, 128, 96, 64,
+ * 48, 32 or 16) of least modelled time, ceil(tiles / 256) x ((T + 32)^2 +
+ * 4096), or 0 when none fits. */
+kk_status kk_tri_set_tile(kk_sim *h, uint32_t cols, uint32_t rows);
+kk_status kk_tri_get_tile(kk_sim *h, uint32_t *cols, uint32_t *rows);
 
 /* Sites per row and rows (H == L except for kk_create_triangular_ex). */
 kk_status kk_shape(kk_sim *h, uint32_t *L, uint32_t *H);

@@ -336,7 +336,12 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
     }
     if (n > 0) h->epoch += 1;
     for (uint64_t k = 0; k < n; ++k) {
-      if (h->geom == 1) {
+      if (h->geom == 1 && h->tri_tw > 0) {
+        KK_HIP(launch_tri_tile_sweep(static_cast<const uint8_t*>(h->lat[h->cur]),
+                                     static_cast<uint8_t*>(h->lat[h->cur ^ 1]), h->L, h->H, h->tri_tw, h->tri_tr,
+                                     h->k0, h->k1, h->t, h->tacc, h->partials, h->stream));
+        h->cur ^= 1;
+      } else if (h->geom == 1) {
         for (int ph = 0; ph < 16; ++ph)
           KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->H, h->k0, h->k1, h->t, ph,
                                   h->tacc, h->partials, h->stream));
@@ -360,7 +365,7 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
       (void)hipEventDestroy(ev[0]);
       (void)hipEventDestroy(ev[1]);
     }
-    if (launches) *launches = (h->geom == 1 ? 16 : 7) * n;
+    if (launches) *launches = (h->geom == 1 ? (h->tri_tw > 0 ? 1 : 16) : 7) * n;
     return KK_OK;
   }
   SweepParams p{};
@@ -419,6 +424,27 @@ kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t 
   KK_HIP(hipStreamSynchronize(h->stream));
   for (auto x : v) h->accepted_base += x;
   return KK_OK;
+}
+
+// Whole-sweep tile of a triangular lattice.  A workgroup works on (T + 32)^2
+// cells per phase on average (its window shrinks from T + 66 to T + 2 across
+// the 16 phases), plus a fixed cost per phase; a CU runs about one
+// workgroup's worth of cells at a time, so the sweep takes about
+// ceil(tiles / 256) of those.  Pick the square tile of least modelled cost
+// (ties: the larger), or 0 -- one launch per class -- when no tile fits.
+void tri_default_tile(int L, int H, int* tw, int* tr) {
+  static const int cand[] = {320, 256, 192, 160, 128, 96, 64, 48, 32, 16};
+  double best = 0.0;
+  *tw = *tr = 0;
+  for (int c : cand) {
+    if (!tri_tile_fits(L, H, c, c)) continue;
+    const double tiles = (double)((L + c - 1) / c) * (double)((H + c - 1) / c);
+    const double cost = std::ceil(tiles / 256.0) * ((double)(c + 32) * (c + 32) + 4096.0);
+    if (*tw == 0 || cost < best) {
+      best = cost;
+      *tw = *tr = c;
+    }
+  }
 }
 
 uint64_t place_count(int L, int H, double composition) {
@@ -526,7 +552,7 @@ kk_status kk_create_triangular_ex(kk_sim** out, uint32_t L, uint32_t H, uint32_t
   if (!(composition >= 0.0 && composition <= 1.0))
     return set_error(KK_EINVAL, "composition must lie in [0, 1]");
   if (!std::isfinite(omega_kT)) return set_error(KK_EINVAL, "omega must be finite");
-  if ((uint64_t)L * H > 0xFFFFFFF0ull || L > 65535 || H > 65535)
+  if ((uint64_t)L * H > 0x7FFFFFFFull || L > 65535 || H > 65535)
     return set_error(KK_EINVAL, "lattice too large (%u x %u)", L, H);
   if (scheme == KK_TRI_CLASSES) {
     if (L < 4 || L % 8 != 4 || H < 4 || H % 4 != 0)
@@ -538,8 +564,34 @@ kk_status kk_create_triangular_ex(kk_sim** out, uint32_t L, uint32_t H, uint32_t
   } else {
     return set_error(KK_EINVAL, "unknown scheme %u", scheme);
   }
-  return create_handle(out, L, H, scheme == KK_TRI_CLASSES ? 1 : 2, composition, omega_kT, seed, kLayoutInt8,
-                       hip_stream);
+  const kk_status st = create_handle(out, L, H, scheme == KK_TRI_CLASSES ? 1 : 2, composition, omega_kT, seed,
+                                     kLayoutInt8, hip_stream);
+  if (st == KK_OK && scheme == KK_TRI_CLASSES) tri_default_tile((int)L, (int)H, &(*out)->tri_tw, &(*out)->tri_tr);
+  return st;
+}
+
+kk_status kk_tri_set_tile(kk_sim* h, uint32_t cols, uint32_t rows) {
+  KK_GUARD(h);
+  if (h->geom != 1) return set_error(KK_EINVAL, "tiles apply to the triangular class schedule only");
+  if (cols == 0) {
+    h->tri_tw = h->tri_tr = 0;
+    return KK_OK;
+  }
+  if (!tri_tile_fits(h->L, h->H, (int)cols, (int)rows))
+    return set_error(KK_EINVAL, "tile %u x %u does not fit: needs >= 16 each, cols + %u <= L, rows + %u <= H and %zu "
+                     "window bytes <= 159 KiB", cols, rows, 2 * kTriHalo, 2 * kTriHalo,
+                     tri_window_bytes(cols, rows));
+  h->tri_tw = (int)cols;
+  h->tri_tr = (int)rows;
+  return KK_OK;
+}
+
+kk_status kk_tri_get_tile(kk_sim* h, uint32_t* cols, uint32_t* rows) {
+  KK_GUARD(h);
+  if (h->geom != 1) return set_error(KK_EINVAL, "tiles apply to the triangular class schedule only");
+  if (cols) *cols = (uint32_t)h->tri_tw;
+  if (rows) *rows = (uint32_t)h->tri_tr;
+  return KK_OK;
 }
 
 kk_status kk_create_triangular(kk_sim** out, uint32_t L, double composition, double omega_kT, uint64_t seed,

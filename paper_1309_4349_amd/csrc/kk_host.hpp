@@ -21,6 +21,7 @@ struct TileConfig {
 kk_status set_error(kk_status st, const char* fmt, ...);
 void acceptance_table(double omega, uint64_t T[7], Accept* acc);
 uint64_t place_count(int L, int H, double composition);
+void tri_default_tile(int L, int H, int* tw, int* tr);
 int max_threads(int ku);
 bool cyclic_fits(int L);
 void default_tile(int L, int layout, TileConfig* tc);
@@ -56,6 +57,7 @@ struct kk_sim {
   int geom = 0;                          // 0 square torus; triangular helical int8 ring: 1 with the
                                          // conflict-free 16 classes, 2 with the literal MPKK cover
   kk::TriAccept tacc{};                  // triangular thresholds
+  int tri_tw = 0, tri_tr = 0;            // whole-sweep tile of the class schedule (0: one launch per class)
   uint64_t epoch = 0;                    // bumped whenever the lattice may change
   uint64_t hist_epoch = ~(uint64_t)0;    // epoch and species of the cached histogram
   int hist_species = -1;

@@ -203,6 +203,145 @@ __global__ __launch_bounds__(256) void tri_similar(const uint8_t* s, uint32_t L,
   if ((threadIdx.x & 63) == 0 && a) atomicAdd(out, a);
 }
 
+// ---------------------------------------------------------------------------
+// One whole sweep of the 16 classes in one launch.  Each workgroup owns a tile
+// of TW x TR sites (columns x0 .. x0+TW-1 of rows y0 .. y0+TR-1; the last tile
+// of a row or column may be narrower) and holds in LDS the window of the ring
+// around it: kTriHalo more rows and columns on every side, read from `in`.
+// Window cell (r, c) is ring site (y0 - kTriHalo + r) * L + x0 - kTriHalo + c
+// mod N, so the six neighbours are (r, c +- 1), (r +- 1, c), (r +- 1, c -+ 1)
+// everywhere in the window, across row ends included.  The workgroup runs the
+// 16 phases on its window; a phase only needs centres within one step of the
+// cells that must stay exact, whose reads lie within two steps, so the exact
+// region shrinks by two cells per phase: phase p works on the cells at least
+// 2p + 2 from the window edge, and after 16 phases the cells at least 33 from
+// the edge -- the tile -- hold exactly what the in-place class sweep gives.
+// The tile is then written to `out`.  Centres are counted as accepted only in
+// the tile, so every attempt of the sweep is counted once.  Needs the window
+// to fit the ring: TW + 2 kTriHalo <= L and TR + 2 kTriHalo <= H.
+__global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                       uint32_t L, uint32_t H, uint32_t TW, uint32_t TR, uint32_t ntx,
+                                                       uint32_t k0, uint32_t k1, uint64_t t, TriAccept acc,
+                                                       unsigned long long* partials) {
+  extern __shared__ uint8_t win[];
+  __shared__ uint32_t perm_s[16], thr_s[11];
+  __shared__ uint32_t all_s;
+  __shared__ unsigned long long red[16];
+  const uint32_t N = L * H;
+  const uint32_t WC = TW + 2 * kTriHalo, WR = TR + 2 * kTriHalo, S = tri_window_stride(TW);
+  const uint32_t tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const uint32_t x0 = tx * TW, y0 = ty * TR;
+  const uint32_t TWe = min(TW, L - x0), TRe = min(TR, H - y0);
+  // ring index of window cell (0, 0)
+  const uint32_t base =
+      (uint32_t)(((uint64_t)y0 * L + x0 + 2ull * N - (uint64_t)kTriHalo * L - kTriHalo) % (uint64_t)N);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  if (threadIdx.x < 64) {
+    const uint32_t c = tri_order(k0, k1, t, (int)(threadIdx.x & 15u));
+    if (threadIdx.x < 16) perm_s[threadIdx.x] = c;
+  } else if (threadIdx.x < 64 + 11) {
+    const uint32_t n = threadIdx.x - 64;
+    const uint64_t T = acc.T[n];
+    thr_s[n] = T >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)T;
+    const uint32_t always = (uint32_t)__ballot(T >= 0x100000000ull);  // lanes 0..10 of wave 1
+    if (n == 0) all_s = always;
+  }
+  // the window: each wave takes two rows at a time and issues all of their
+  // byte loads (up to 16 per lane) before storing any, so the loads overlap
+  for (uint32_t r0 = 2 * wave; r0 < WR; r0 += 2 * nwaves) {
+    for (uint32_t c0 = 0; c0 < WC; c0 += 512) {
+      uint8_t v[16];
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        // out-of-window lanes read site 0 and drop it: no branch around the load
+        const uint32_t r = r0 + (k >> 3), c = c0 + lane + 64u * (k & 7u);
+        const bool ok = r < WR && c < WC;
+        uint32_t rb = base + (ok ? r : 0u) * L;
+        rb = rb >= N ? rb - N : rb;
+        uint32_t i = rb + (ok ? c : 0u);
+        i = i >= N ? i - N : i;
+        v[k] = in[i];
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        const uint32_t r = r0 + (k >> 3), c = c0 + lane + 64u * (k & 7u);
+        if (r < WR && c < WC) win[r * S + c] = v[k];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t always = all_s;
+  const uint32_t tl = (uint32_t)t, th = ctr_hi(t, kTagTri);
+  // per-lane parts of the row addresses; the wave index is uniform, so the
+  // work-item arithmetic below stays in scalar registers
+  const uint32_t lane_ring = lane * L, lane_win = lane * S;
+  const uint32_t wave_u = __builtin_amdgcn_readfirstlane(wave);
+  unsigned long long cnt = 0;
+  for (int p = 0; p < 16; ++p) {
+    const uint32_t cls = perm_s[p];
+    const uint32_t lo = 2u * (uint32_t)p + 2u;
+    const uint32_t rhi = WR - lo, chi = WC - lo;
+    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 15u) >> 4;
+    for (uint32_t it = wave_u; it < nrg * Q; it += nwaves) {
+      const uint32_t rg = it / Q, q = it - rg * Q;
+      const uint32_t r0 = lo + rg * 64u;  // uniform first row of the item
+      const uint32_t r = r0 + lane;
+      if (r >= rhi) continue;
+      uint32_t rb0 = base + r0 * L;
+      rb0 = rb0 >= N ? rb0 - N : rb0;
+      uint32_t rb = rb0 + lane_ring;
+      rb = rb >= N ? rb - N : rb;
+      const uint32_t c = lo + ((cls - rb - lo) & 15u) + 16u * q;
+      if (c >= chi) continue;
+      uint32_t i = rb + c;
+      i = i >= N ? i - N : i;
+      const Philox4 rr = philox10(i >> 1, 0u, tl, th, k0, k1);
+      const uint32_t wd = (i & 1u) ? rr.z : rr.x, u = (i & 1u) ? rr.w : rr.y;
+      const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
+      const uint32_t a = r0 * S + lane_win + c;
+      const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
+      const uint32_t b = (d & 1u) ? a - mag : a + mag;
+      // sites hold 0 or 1, so x ^ v counts an unlike neighbour
+      auto site = [&](uint32_t k) {
+        const uint32_t x = win[k];
+        __builtin_assume(x <= 1u);
+        return x;
+      };
+      const uint32_t va = site(a), vb = site(b);
+      if (va == vb) continue;
+      // the a-b bond is unlike and appears once in each neighbourhood
+      const uint32_t n = (site(a + 1) ^ va) + (site(a - 1) ^ va) + (site(a + S) ^ va) + (site(a - S) ^ va) +
+                         (site(a + S - 1) ^ va) + (site(a - S + 1) ^ va) + (site(b + 1) ^ vb) + (site(b - 1) ^ vb) +
+                         (site(b + S) ^ vb) + (site(b - S) ^ vb) + (site(b + S - 1) ^ vb) + (site(b - S + 1) ^ vb) -
+                         2u;
+      if (u < thr_s[n] || ((always >> n) & 1u)) {
+        win[a] = (uint8_t)vb;
+        win[b] = (uint8_t)va;
+        cnt += (r - kTriHalo < TRe) & (c - kTriHalo < TWe);
+      }
+    }
+    __syncthreads();
+  }
+  // the tile
+  for (uint32_t r = kTriHalo + wave; r < kTriHalo + TRe; r += nwaves) {
+    uint32_t rb = base + r * L;
+    if (rb >= N) rb -= N;
+    for (uint32_t c = kTriHalo + lane; c < kTriHalo + TWe; c += 64) {
+      uint32_t i = rb + c;
+      if (i >= N) i -= N;
+      out[i] = win[r * S + c];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+  if (lane == 0) red[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (uint32_t w = 0; w < nwaves; ++w) tot += red[w];
+    if (tot) atomicAdd(&partials[blockIdx.x % kTriPartials], tot);
+  }
+}
+
 int tri_grid(size_t n) {
   const size_t g = (n + 255) / 256;
   return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
@@ -215,6 +354,16 @@ hipError_t launch_tri_phase(uint8_t* lat, int L, int H, uint32_t k0, uint32_t k1
   const uint32_t N = (uint32_t)L * (uint32_t)H;
   hipLaunchKernelGGL(tri_phase, dim3(tri_grid(N / 16)), dim3(256), 0, stream, lat, (uint32_t)L, N, k0, k1, t, p, acc,
                      partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_tile_sweep(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
+                                uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
+                                hipStream_t stream) {
+  if (!tri_tile_fits(L, H, TW, TR)) return hipErrorInvalidValue;
+  const uint32_t ntx = ((uint32_t)L + TW - 1) / TW, nty = ((uint32_t)H + TR - 1) / TR;
+  hipLaunchKernelGGL(tri_tile_sweep, dim3(ntx * nty), dim3(1024), tri_window_bytes(TW, TR), stream, in, out,
+                     (uint32_t)L, (uint32_t)H, (uint32_t)TW, (uint32_t)TR, ntx, k0, k1, t, acc, partials);
   return hipGetLastError();
 }
 

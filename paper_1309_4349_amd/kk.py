@@ -24,7 +24,8 @@ _SCHEMES = {"classes": TRI_CLASSES, "mpkk": TRI_MPKK}
 _STARTS = {"random": START_RANDOM, "segregated": START_SEGREGATED}
 
 EXPORTS = [
-    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds",
+    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds", "kk_tri_set_tile",
+    "kk_tri_get_tile",
     "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info",
     "kk_set_tile", "kk_get_tile", "kk_autotune",
@@ -111,6 +112,8 @@ def load(path: str = LIB_PATH):
         "kk_create_triangular": [PP, U32, D, D, U64, P],
         "kk_create_triangular_ex": [PP, U32, U32, U32, D, D, U64, P],
         "kk_shape": [P, u32p, u32p],
+        "kk_tri_set_tile": [P, U32, U32],
+        "kk_tri_get_tile": [P, u32p, u32p],
         "kk_tri_thresholds": [P, u64p],
         "kk_geometry": [P, u32p],
         "kk_restart": [P, U32],
@@ -215,6 +218,15 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+    def tri_set_tile(self, cols: int, rows: int = 0):
+        """Whole-sweep tile of the triangular class schedule (cols = 0: one launch per class)."""
+        _check(load().kk_tri_set_tile(self._h, cols, rows or cols))
+
+    def tri_get_tile(self) -> Tuple[int, int]:
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().kk_tri_get_tile(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def restart(self, start: str = "random"):
         """Back to a starting lattice ("random" or "segregated"), t = 0."""

@@ -83,3 +83,46 @@ def test_tri_rejects_square_only_calls():
     for L in (8, 16, 0, 6):
         with pytest.raises(kk.KKError):
             kk.Sim(L, 0.5, 1.0, 1, geometry="triangular")
+
+
+@pytest.mark.parametrize("L,H,tile,x,w,n", [
+    (100, 100, (16, 16), 0.5, 0.8, 7), (124, 84, (40, 18), 0.45, 1.2, 5), (204, 204, (128, 128), 0.5, 0.6, 6),
+    (404, 412, (256, 256), 0.3, 0.9, 4), (404, 404, (96, 160), 0.5, -0.5, 5), (132, 200, (66, 134), 0.5, 0.0, 3),
+])
+def test_tri_whole_sweep_tiles_match_oracle(L, H, tile, x, w, n):
+    # one launch per sweep on LDS windows: ragged tiles, rectangles, windows across row ends
+    print(f"case tri tiles L={L} H={H} tile={tile}", flush=True)
+    seed = wl.job_seed(43, L * 1000 + H)
+    s = kk.Sim(L, x, w, seed, geometry="triangular", rows=H)
+    s.tri_set_tile(*tile)
+    assert s.tri_get_tile() == tile
+    ref = oracle.init_rect(L, H, x, seed)
+    acc = oracle.tri_sweeps(ref, w, seed, 0, n)
+    ms, launches = s.sweep_timed(n)
+    assert launches == n
+    assert np.array_equal(s.get_lattice(), ref)
+    assert s.stats() == (n, n * L * H, acc)
+    assert s.energy()[0] == oracle.tri_energy(ref)
+    assert s.cluster_hist(1) == oracle.tri_cluster_hist(ref, 1)
+    # switching to one launch per class mid-run continues the same chain
+    s.tri_set_tile(0)
+    s.sweep(2)
+    oracle.tri_sweeps(ref, w, seed, n, 2)
+    assert np.array_equal(s.get_lattice(), ref)
+    s.close()
+
+
+def test_tri_default_tiles_and_rejections():
+    s = kk.Sim(4092, 0.5, 0.88, 5, geometry="triangular")
+    assert s.tri_get_tile() == (256, 256)
+    assert kk.Sim(1028, 0.5, 0.88, 5, geometry="triangular").tri_get_tile() == (96, 96)
+    for bad in ((15, 64), (64, 15), (4092, 64), (400, 400)):
+        with pytest.raises(kk.KKError):
+            s.tri_set_tile(*bad)
+    s.close()
+    assert kk.Sim(100, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() in ((16, 16), (32, 32))
+    assert kk.Sim(76, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() == (0, 0)   # 16 + 66 > 76
+    m = kk.Sim(10, 0.5, 1.0, 1, geometry="triangular", rows=7, scheme="mpkk")
+    with pytest.raises(kk.KKError):
+        m.tri_set_tile(16, 16)
+    m.close()
