@@ -139,7 +139,8 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
            "value": rate, "unit": "attempts/s", "n_unlike_over_3N": nab / (3 * N),
            "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
                         "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
-                        "traffic": None, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase", "kernel_us": round(per_launch_s * 1e6, 3),
+                        "traffic": None, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase",
+                        "kernel_us": round(per_launch_s * 1e6, 3),
                         "launches": int(launches), "ops_per_attempt": TRI_OPS_PER_ATTEMPT,
                         "tile": {"cols": sim_tile[0], "rows": sim_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}

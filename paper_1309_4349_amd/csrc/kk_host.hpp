@@ -8,6 +8,7 @@
 
 #include "../../include/kk.h"
 #include "kk_kernels.hpp"
+#include "kk_tri.hpp"
 
 namespace kk {
 

@@ -93,37 +93,6 @@ constexpr int kSmallSizes = 4096;
 hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, const CclBuffers& b, bool triangular,
                       hipStream_t stream);
 
-// Triangular lattice, helical boundaries (kk_tri.hip): H rows of L sites on
-// one ring of N = L*H.  Conflict-free classes: one launch per phase.  The
-// literal MPKK variant: one launch per iteration, ping-pong buffers.
-constexpr int kTriPartials = 64;  // accepted-move sums, indexed by workgroup % kTriPartials
-struct TriAccept {
-  uint64_t T[11];  // U < T[n] accepts, n = unlike neighbours of the pair (each excluding the other)
-};
-hipError_t launch_tri_phase(uint8_t* lat, int L, int H, uint32_t k0, uint32_t k1, uint64_t t, int p,
-                            const TriAccept& acc, unsigned long long* partials, hipStream_t stream);
-// Whole-sweep tiles (16 phases per launch on an LDS window, `in` -> `out`).
-constexpr uint32_t kTriHalo = 33;  // 2 cells per phase, plus 1 for the first phase's reads
-__host__ __device__ inline uint32_t tri_window_stride(uint32_t TW) {
-  const uint32_t s = (TW + 2 * kTriHalo + 3u) & ~3u;  // whole words, an odd number of them
-  return ((s >> 2) & 1u) ? s : s + 4u;
-}
-__host__ __device__ inline size_t tri_window_bytes(uint32_t TW, uint32_t TR) {
-  return (size_t)tri_window_stride(TW) * (TR + 2 * kTriHalo);
-}
-inline bool tri_tile_fits(int L, int H, int TW, int TR) {
-  return TW >= 16 && TR >= 16 && TW + 2 * (int)kTriHalo <= L && TR + 2 * (int)kTriHalo <= H &&
-         tri_window_bytes((uint32_t)TW, (uint32_t)TR) <= 160u * 1024u - 1024u;
-}
-hipError_t launch_tri_tile_sweep(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
-                                uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
-                                hipStream_t stream);
-hipError_t launch_mpkk_iteration(const uint8_t* in, uint8_t* out, int L, int H, uint32_t k0, uint32_t k1, uint64_t t,
-                                 int j, const TriAccept& acc, unsigned long long* partials, hipStream_t stream);
-hipError_t launch_tri_energy(const uint8_t* lat, int L, int H, unsigned long long* out, hipStream_t stream);
-hipError_t launch_tri_similar(const uint8_t* lat, int L, int H, uint32_t k0, uint32_t k1, uint64_t t,
-                              unsigned long long* out, hipStream_t stream);
-
 // Segregated start: sites 0 .. n1-1 (index y*L + x) set to 1, the rest 0.
 hipError_t launch_fill_segregated(void* lat, int layout, int L, int H, uint64_t n1, hipStream_t stream);
 

@@ -34,6 +34,7 @@
 
 #include "kk_common.hpp"
 #include "kk_kernels.hpp"
+#include "kk_tri.hpp"
 
 namespace kk {
 namespace {
