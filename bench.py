@@ -57,16 +57,21 @@ OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
-PROFILED_TRAFFIC = {"sources_sha256_prefix": "8bf0ed816067e372", "tile": (16, 128, 2),
-                    "bytes_per_launch": 10924357}
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "79d807e8d4da7bbd", "tile": (16, 128, 2),
+                    "bytes_per_launch": 10905061}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
+# The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
+# 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "94560315aeefbcd3", "tile": (256, 256),
+                        "bytes_per_launch": 50472014}
+TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 
 
-def kernel_sources_sha() -> str:
+def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_1309_4349_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -135,11 +140,15 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
     hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
     nab, _ = sim.energy()
     sim.close()
+    traffic = None
+    if (kernel_sources_sha(TRI_KERNEL_SOURCES) == TRI_PROFILED_TRAFFIC["sources_sha256_prefix"]
+            and tuple(sim_tile) == TRI_PROFILED_TRAFFIC["tile"]):
+        traffic = TRI_PROFILED_TRAFFIC["bytes_per_launch"]
     out = {"workload": f"triangular helical {L}x{L} int8, x={x}, omega={w}, {sweeps} sweeps",
            "value": rate, "unit": "attempts/s", "n_unlike_over_3N": nab / (3 * N),
            "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
                         "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
-                        "traffic": None, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase",
+                        "traffic": traffic, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase",
                         "kernel_us": round(per_launch_s * 1e6, 3),
                         "launches": int(launches), "ops_per_attempt": TRI_OPS_PER_ATTEMPT,
                         "tile": {"cols": sim_tile[0], "rows": sim_tile[1]},
