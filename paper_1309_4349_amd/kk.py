@@ -330,7 +330,8 @@ class _Borrowed(Sim):
 
     def __init__(self, handle, L, omega, seed):
         self._h = handle
-        self.L = L
+        self.L = self.H = L
+        self.geometry = "square"
         self.omega = omega
         self.seed = seed
 
