@@ -324,27 +324,42 @@ kk_status reset_partials(kk_sim* h) {
 
 // Launch sweeps [h->t, h->t + n) on the handle's stream.  With `timing`, an
 // event pair brackets every launch and the kernel time is accumulated.
+// A pair of HIP events, destroyed on every way out.
+struct EventPair {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~EventPair() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
+  EventPair tm;
+  if (kernel_ms) {
+    *kernel_ms = 0.0;
+    KK_HIP(hipEventCreate(&tm.ev[0]));
+    KK_HIP(hipEventCreate(&tm.ev[1]));
+    KK_HIP(hipEventRecord(tm.ev[0], h->stream));
+  }
+  if (n > 0) h->epoch += 1;
+  uint64_t nl = 0;
+  const uint64_t sites = (uint64_t)h->L * (uint64_t)h->H;
   if (h->geom != 0) {
-    // triangular: 16 launches (one per class) per sweep in place, or 7
-    // synchronous MPKK iterations per step between the two buffers
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    if (kernel_ms) {
-      KK_HIP(hipEventCreate(&ev[0]));
-      KK_HIP(hipEventCreate(&ev[1]));
-      KK_HIP(hipEventRecord(ev[0], h->stream));
-    }
-    if (n > 0) h->epoch += 1;
+    // triangular: one whole-sweep tile launch, or 16 launches (one per class)
+    // in place, per sweep; literal MPKK: 7 synchronous iterations per step
+    // between the two buffers
     for (uint64_t k = 0; k < n; ++k) {
       if (h->geom == 1 && h->tri_tw > 0) {
         KK_HIP(launch_tri_tile_sweep(static_cast<const uint8_t*>(h->lat[h->cur]),
                                      static_cast<uint8_t*>(h->lat[h->cur ^ 1]), h->L, h->H, h->tri_tw, h->tri_tr,
                                      h->k0, h->k1, h->t, h->tacc, h->partials, h->stream));
         h->cur ^= 1;
+        nl += 1;
       } else if (h->geom == 1) {
         for (int ph = 0; ph < 16; ++ph)
           KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->H, h->k0, h->k1, h->t, ph,
                                   h->tacc, h->partials, h->stream));
+        nl += 16;
       } else {
         for (int j = 0; j < 7; ++j) {
           KK_HIP(launch_mpkk_iteration(static_cast<const uint8_t*>(h->lat[h->cur]),
@@ -352,61 +367,41 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
                                        h->tacc, h->partials, h->stream));
           h->cur ^= 1;
         }
+        nl += 7;
       }
       h->t += 1;
-      h->attempts += (uint64_t)h->L * (uint64_t)h->H;
+      h->attempts += sites;
     }
-    if (kernel_ms) {
-      KK_HIP(hipEventRecord(ev[1], h->stream));
-      KK_HIP(hipEventSynchronize(ev[1]));
-      float ms = 0.f;
-      KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-      *kernel_ms = ms;
-      (void)hipEventDestroy(ev[0]);
-      (void)hipEventDestroy(ev[1]);
+  } else {
+    SweepParams p{};
+    const int threads = tile_geometry(h->L, h->tile, &p);
+    p.accepted = h->partials;
+    p.k0 = h->k0;
+    p.k1 = h->k1;
+    p.acc = h->acc;
+    const uint64_t per_launch = h->tile.cyclic ? 256 : 1;
+    while (n > 0) {
+      const uint64_t k = n < per_launch ? n : per_launch;
+      p.src = h->lat[h->cur];
+      p.dst = h->lat[h->cur ^ 1];
+      p.t0 = h->t;
+      p.nsweeps = (int)k;
+      KK_HIP(launch_sweep(p, h->layout, h->tile.cyclic, h->tile.ku, threads, h->stream));
+      h->cur ^= 1;
+      h->t += k;
+      h->attempts += k * sites;
+      n -= k;
+      ++nl;
     }
-    if (launches) *launches = (h->geom == 1 ? (h->tri_tw > 0 ? 1 : 16) : 7) * n;
-    return KK_OK;
-  }
-  SweepParams p{};
-  const int threads = tile_geometry(h->L, h->tile, &p);
-  p.accepted = h->partials;
-  p.k0 = h->k0;
-  p.k1 = h->k1;
-  p.acc = h->acc;
-  const uint64_t per_launch = h->tile.cyclic ? 256 : 1;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  if (kernel_ms) {
-    KK_HIP(hipEventCreate(&ev[0]));
-    KK_HIP(hipEventCreate(&ev[1]));
-    *kernel_ms = 0.0;
-  }
-  uint64_t nl = 0;
-  if (n > 0) h->epoch += 1;
-  if (kernel_ms) KK_HIP(hipEventRecord(ev[0], h->stream));
-  while (n > 0) {
-    const uint64_t k = n < per_launch ? n : per_launch;
-    p.src = h->lat[h->cur];
-    p.dst = h->lat[h->cur ^ 1];
-    p.t0 = h->t;
-    p.nsweeps = (int)k;
-    KK_HIP(launch_sweep(p, h->layout, h->tile.cyclic, h->tile.ku, threads, h->stream));
-    h->cur ^= 1;
-    h->t += k;
-    h->attempts += k * (uint64_t)h->L * (uint64_t)h->L;
-    n -= k;
-    ++nl;
   }
   if (kernel_ms) {
     // one event pair around the back-to-back launches: the elapsed time is
     // their summed duration plus whatever gaps the device leaves between them
-    KK_HIP(hipEventRecord(ev[1], h->stream));
-    KK_HIP(hipEventSynchronize(ev[1]));
+    KK_HIP(hipEventRecord(tm.ev[1], h->stream));
+    KK_HIP(hipEventSynchronize(tm.ev[1]));
     float ms = 0.f;
-    KK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    KK_HIP(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
     *kernel_ms = ms;
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
   }
   if (launches) *launches = nl;
   return KK_OK;
