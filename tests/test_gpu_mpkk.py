@@ -79,3 +79,21 @@ def test_invalid_shapes_are_rejected():
     for L, H, scheme in ((11, 7, "mpkk"), (10, 8, "mpkk"), (12, 6, "classes"), (8, 8, "classes"), (10, 0, "mpkk")):
         with pytest.raises(kk.KKError):
             kk.Sim(L, 0.5, 1.0, 1, geometry="triangular", rows=H, scheme=scheme)
+
+
+def test_mpkk_full_size_4098x4095():
+    # the benchmarked configuration: 4098 x 4095 ring, x = 0.5, omega = 0.88
+    L, H, x, w, seed = 4098, 4095, 0.5, 0.88, 0x13094349
+    print("case mpkk full size 4098x4095", flush=True)
+    s = kk.Sim(L, x, w, seed, geometry="triangular", rows=H, scheme="mpkk")
+    ref = oracle.init_rect(L, H, x, seed)
+    assert np.array_equal(s.get_lattice(), ref)
+    acc = oracle.mpkk_steps(ref, w, seed, 0, 2)
+    s.sweep(2)
+    assert np.array_equal(s.get_lattice(), ref)
+    assert s.stats() == (2, 2 * L * H, acc)
+    s.sweep(48)
+    got = s.get_lattice()
+    assert int(got.sum()) == oracle.n_ones_rect(L, H, x)
+    assert s.energy()[0] == oracle.tri_energy(got)
+    s.close()

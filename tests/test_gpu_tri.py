@@ -126,3 +126,32 @@ def test_tri_default_tiles_and_rejections():
     with pytest.raises(kk.KKError):
         m.tri_set_tile(16, 16)
     m.close()
+
+
+def test_tri_full_size_4092():
+    # the benchmarked configuration: 4092^2, x = 0.5, omega = 0.88, default 256 x 256 tiles
+    L, x, w, seed = 4092, 0.5, 0.88, 0x13094349
+    print("case tri full size 4092", flush=True)
+    s = kk.Sim(L, x, w, seed, geometry="triangular")
+    assert s.tri_get_tile() == (256, 256)
+    ref = oracle.init(L, x, seed)
+    assert np.array_equal(s.get_lattice(), ref)
+    acc = oracle.tri_sweeps(ref, w, seed, 0, 3)
+    s.sweep(3)
+    got = s.get_lattice()
+    assert np.array_equal(got, ref)
+    assert s.stats() == (3, 3 * L * L, acc)
+    # a longer run: composition, N_AB recount, histogram sum rule, resume
+    s.sweep(197)
+    got = s.get_lattice()
+    assert int(got.sum()) == oracle.n_ones(L, x)
+    assert s.energy()[0] == oracle.tri_energy(got)
+    h = s.cluster_hist(1)
+    assert sum(k * c for k, c in h) == oracle.n_ones(L, x)
+    b = kk.Sim(L, x, w, seed, geometry="triangular")
+    b.set_lattice(got, 200)
+    s.sweep(5)
+    b.sweep(5)
+    assert np.array_equal(s.get_lattice(), b.get_lattice())
+    s.close()
+    b.close()
