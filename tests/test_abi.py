@@ -84,3 +84,39 @@ def test_null_handles_of_the_batch_server_and_tuner_calls_are_rejected():
     assert lib.kk_server_get_stats(None, ctypes.byref(st)) == kk.KK_EINVAL
     lib.kk_server_destroy(None)
     assert lib.kk_last_error()
+
+
+@pytest.mark.parametrize("L,H,scheme,x,w", [
+    (8, 8, 0, 0.5, 0.5), (12, 6, 0, 0.5, 0.5), (0, 12, 0, 0.5, 0.5), (12, 0, 0, 0.5, 0.5),
+    (11, 7, 1, 0.5, 0.5), (10, 8, 1, 0.5, 0.5), (14, 14, 1, 0.5, 0.5), (10, 7, 2, 0.5, 0.5),
+    (12, 12, 0, -0.5, 0.5), (10, 7, 1, 0.5, float("nan")), (65540, 4, 0, 0.5, 0.5), (65532, 65532, 0, 0.5, 0.5),
+])
+def test_triangular_create_rejects_invalid_arguments(L, H, scheme, x, w):
+    # shapes outside the 16-class schedule (L % 8 == 4, H % 4 == 0) or the 7-site cover
+    # (L % 7 in {3, 5}, H % 7 == 0), unknown schemes, bad compositions, omegas and sizes
+    lib = kk.load()
+    h = ctypes.c_void_p(1)
+    st = lib.kk_create_triangular_ex(ctypes.byref(h), L, H, scheme, x, w, 1, None)
+    assert st == kk.KK_EINVAL
+    assert h.value is None
+    assert lib.kk_last_error()
+    if H == L and scheme == 0:
+        assert lib.kk_create_triangular(ctypes.byref(h), L, x, w, 1, None) == kk.KK_EINVAL
+
+
+def test_null_handles_of_the_geometry_calls_are_rejected():
+    lib = kk.load()
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    T = (ctypes.c_uint64 * 11)()
+    assert lib.kk_shape(None, ctypes.byref(a), ctypes.byref(b)) == kk.KK_EINVAL
+    assert lib.kk_geometry(None, ctypes.byref(a)) == kk.KK_EINVAL
+    assert lib.kk_tri_thresholds(None, T) == kk.KK_EINVAL
+    assert lib.kk_tri_set_tile(None, 64, 64) == kk.KK_EINVAL
+    assert lib.kk_tri_get_tile(None, ctypes.byref(a), ctypes.byref(b)) == kk.KK_EINVAL
+    assert lib.kk_restart(None, 0) == kk.KK_EINVAL
+    assert lib.kk_create_triangular_ex(None, 12, 12, 0, 0.5, 0.5, 1, None) == kk.KK_EINVAL
+
+
+def test_borrowed_batch_handles_describe_a_square_lattice():
+    b = kk._Borrowed(None, 64, 0.5, 1)
+    assert (b.L, b.H, b.geometry) == (64, 64, "square")
