@@ -131,7 +131,10 @@ bool tile_valid(int L, const TileConfig& tc, std::string* why) {
   if (tc.cyclic) {
     if (!cyclic_fits(L)) { *why = "cyclic tile needs L % 32 == 0 and (L/2)*(L/32) <= 1536"; return false; }
   } else {
-    if (tc.tww < 1 || tc.th < 2 || (tc.th & 1)) { *why = "tile_words >= 1 and an even tile_rows >= 2 needed"; return false; }
+    if (tc.tww < 1 || tc.th < 2 || (tc.th & 1)) {
+      *why = "tile_words >= 1 and an even tile_rows >= 2 needed";
+      return false;
+    }
   }
   SweepParams p{};
   const int threads = tile_geometry(L, tc, &p);

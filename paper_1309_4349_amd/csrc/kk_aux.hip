@@ -106,8 +106,9 @@ __global__ __launch_bounds__(256) void radix_hist(const uint64_t* keys, size_t n
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, int H, int layout, uint64_t kth, void* lat,
-                                                 unsigned* eq_count, uint32_t* eq_list, unsigned eq_cap) {
+__global__ __launch_bounds__(256) void init_mark(const uint64_t* keys, int L, int H, int layout, uint64_t kth,
+                                                 void* lat, unsigned* eq_count, uint32_t* eq_list,
+                                                 unsigned eq_cap) {
   if (layout == kLayoutBits) {
     const int wpr = L >> 5;
     const size_t nw = (size_t)H * wpr;
@@ -189,7 +190,8 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
   }
 }
 
-__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species, uint32_t* parent) {
+__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species,
+                                                uint32_t* parent) {
   const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);

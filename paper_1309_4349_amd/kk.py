@@ -24,7 +24,8 @@ _SCHEMES = {"classes": TRI_CLASSES, "mpkk": TRI_MPKK}
 _STARTS = {"random": START_RANDOM, "segregated": START_SEGREGATED}
 
 EXPORTS = [
-    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds", "kk_tri_set_tile",
+    "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds",
+    "kk_tri_set_tile",
     "kk_tri_get_tile",
     "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info",

@@ -104,7 +104,8 @@ def test_batch_autotune_restores_state():
 
 @pytest.mark.parametrize("specs", [
     # (L, layout, composition, omega, sweeps)
-    [(64, "int8", 0.0, 0.9, 5), (96, "bitpacked", 1.0, 0.9, 5), (320, "bitpacked", 0.5, 0.7, 0), (32, "bitpacked", 0.5, 1.1, 9)],
+    [(64, "int8", 0.0, 0.9, 5), (96, "bitpacked", 1.0, 0.9, 5), (320, "bitpacked", 0.5, 0.7, 0),
+     (32, "bitpacked", 0.5, 1.1, 9)],
     [(160, "int8", 0.5, 0.5, 70)],
     [(64, "bitpacked", 0.4, 0.8, 3), (128, "int8", 0.6, -0.5, 130), (288, "bitpacked", 0.5, 0.88, 65)],
     [(36, "int8", 0.5, 0.3, 65), (4, "int8", 0.5, 2.0, 7), (12, "int8", 0.25, 0.0, 11)],
