@@ -172,8 +172,8 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
 
 # One literal-MPKK attempt: one Philox block per two domains (20), k draw
 # amortised (0), direction and uniform (3), 12 neighbour indices (24), 12
-# unlike tests and their sum (24), threshold (3), the 7-site domain copy with
-# the swap folded in (6 indices + 7 selects = 13) -> 87.
+# unlike tests and their sum (24), threshold (3), writing the domain's result
+# (13) -> 87.
 MPKK_OPS_PER_ATTEMPT = 87.0
 
 
@@ -197,6 +197,7 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rate = steps * N / dt
+    mp_tile = sim.tri_get_tile()
     ms, launches = sim.sweep_timed(50)
     per_launch_s = ms / 1e3 / launches
     per_launch = N * 50 / launches
@@ -207,8 +208,10 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
            "value": rate, "unit": "attempts/s",
            "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
                         "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
-                        "traffic": None, "kernel": "mpkk_iter", "kernel_us": round(per_launch_s * 1e6, 3),
+                        "traffic": None, "kernel": "mpkk_tile_step" if mp_tile[0] else "mpkk_iter",
+                        "kernel_us": round(per_launch_s * 1e6, 3),
                         "launches": int(launches), "ops_per_attempt": MPKK_OPS_PER_ATTEMPT,
+                        "tile": {"cols": mp_tile[0], "rows": mp_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
     log(f"[bench] mpkk {L}x{H}: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
     if cpu:

@@ -363,6 +363,12 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
           KK_HIP(launch_tri_phase(static_cast<uint8_t*>(h->lat[h->cur]), h->L, h->H, h->k0, h->k1, h->t, ph,
                                   h->tacc, h->partials, h->stream));
         nl += 16;
+      } else if (h->tri_tw > 0) {
+        KK_HIP(launch_mpkk_tile_step(static_cast<const uint8_t*>(h->lat[h->cur]),
+                                     static_cast<uint8_t*>(h->lat[h->cur ^ 1]), h->L, h->H, h->tri_tw, h->tri_tr,
+                                     h->k0, h->k1, h->t, h->tacc, h->partials, h->stream));
+        h->cur ^= 1;
+        nl += 1;
       } else {
         for (int j = 0; j < 7; ++j) {
           KK_HIP(launch_mpkk_iteration(static_cast<const uint8_t*>(h->lat[h->cur]),
@@ -424,20 +430,23 @@ kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t 
   return KK_OK;
 }
 
-// Whole-sweep tile of a triangular lattice.  A workgroup works on (T + 32)^2
-// cells per phase on average (its window shrinks from T + 66 to T + 2 across
-// the 16 phases), plus a fixed cost per phase; a CU runs about one
-// workgroup's worth of cells at a time, so the sweep takes about
+// Whole-sweep (or whole-step) tile of a triangular lattice.  A workgroup
+// works on (T + h)^2 cells per phase on average -- its window shrinks from
+// T + 2 halo to about T across the phases, h = 32 for the 16 classes and 21
+// for the 7 MPKK iterations -- plus a fixed cost per phase; a CU runs about
+// one workgroup's worth of cells at a time, so a launch takes about
 // ceil(tiles / 256) of those.  Pick the square tile of least modelled cost
-// (ties: the larger), or 0 -- one launch per class -- when no tile fits.
-void tri_default_tile(int L, int H, int* tw, int* tr) {
+// (ties: the larger), or 0 -- one launch per class or iteration -- when no
+// tile fits.
+void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr) {
   static const int cand[] = {320, 256, 192, 160, 128, 96, 64, 48, 32, 16};
+  const int h = mpkk ? 21 : 32;
   double best = 0.0;
   *tw = *tr = 0;
   for (int c : cand) {
-    if (!tri_tile_fits(L, H, c, c)) continue;
+    if (!(mpkk ? mpkk_tile_fits(L, H, c, c) : tri_tile_fits(L, H, c, c))) continue;
     const double tiles = (double)((L + c - 1) / c) * (double)((H + c - 1) / c);
-    const double cost = std::ceil(tiles / 256.0) * ((double)(c + 32) * (c + 32) + 4096.0);
+    const double cost = std::ceil(tiles / 256.0) * ((double)(c + h) * (c + h) + 4096.0);
     if (*tw == 0 || cost < best) {
       best = cost;
       *tw = *tr = c;
@@ -564,21 +573,25 @@ kk_status kk_create_triangular_ex(kk_sim** out, uint32_t L, uint32_t H, uint32_t
   }
   const kk_status st = create_handle(out, L, H, scheme == KK_TRI_CLASSES ? 1 : 2, composition, omega_kT, seed,
                                      kLayoutInt8, hip_stream);
-  if (st == KK_OK && scheme == KK_TRI_CLASSES) tri_default_tile((int)L, (int)H, &(*out)->tri_tw, &(*out)->tri_tr);
+  if (st == KK_OK) tri_default_tile((int)L, (int)H, scheme == KK_TRI_MPKK, &(*out)->tri_tw, &(*out)->tri_tr);
   return st;
 }
 
 kk_status kk_tri_set_tile(kk_sim* h, uint32_t cols, uint32_t rows) {
   KK_GUARD(h);
-  if (h->geom != 1) return set_error(KK_EINVAL, "tiles apply to the triangular class schedule only");
+  if (h->geom == 0) return set_error(KK_EINVAL, "tiles apply to triangular lattices only");
   if (cols == 0) {
     h->tri_tw = h->tri_tr = 0;
     return KK_OK;
   }
-  if (!tri_tile_fits(h->L, h->H, (int)cols, (int)rows))
+  const bool mp = h->geom == 2;
+  const uint32_t halo = mp ? kMpkkHalo : kTriHalo;
+  const bool fits = mp ? mpkk_tile_fits(h->L, h->H, (int)cols, (int)rows)
+                        : tri_tile_fits(h->L, h->H, (int)cols, (int)rows);
+  if (!fits)
     return set_error(KK_EINVAL, "tile %u x %u does not fit: needs >= 16 each, cols + %u <= L, rows + %u <= H and %zu "
-                     "window bytes <= 159 KiB", cols, rows, 2 * kTriHalo, 2 * kTriHalo,
-                     tri_window_bytes(cols, rows));
+                     "window bytes <= 159 KiB", cols, rows, 2 * halo, 2 * halo,
+                     mp ? mpkk_window_bytes(cols, rows) : tri_window_bytes(cols, rows));
   h->tri_tw = (int)cols;
   h->tri_tr = (int)rows;
   return KK_OK;
@@ -586,7 +599,7 @@ kk_status kk_tri_set_tile(kk_sim* h, uint32_t cols, uint32_t rows) {
 
 kk_status kk_tri_get_tile(kk_sim* h, uint32_t* cols, uint32_t* rows) {
   KK_GUARD(h);
-  if (h->geom != 1) return set_error(KK_EINVAL, "tiles apply to the triangular class schedule only");
+  if (h->geom == 0) return set_error(KK_EINVAL, "tiles apply to triangular lattices only");
   if (cols) *cols = (uint32_t)h->tri_tw;
   if (rows) *rows = (uint32_t)h->tri_tr;
   return KK_OK;

@@ -22,7 +22,7 @@ struct TileConfig {
 kk_status set_error(kk_status st, const char* fmt, ...);
 void acceptance_table(double omega, uint64_t T[7], Accept* acc);
 uint64_t place_count(int L, int H, double composition);
-void tri_default_tile(int L, int H, int* tw, int* tr);
+void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr);
 int max_threads(int ku);
 bool cyclic_fits(int L);
 void default_tile(int L, int layout, TileConfig* tc);

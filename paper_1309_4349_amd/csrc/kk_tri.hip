@@ -343,6 +343,144 @@ __global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// One whole literal-MPKK step (7 iterations) in one launch.  As in
+// tri_tile_sweep, each workgroup owns a TW x TR tile and holds the window of
+// the ring around it, kMpkkHalo more rows and columns on every side.  A cell's
+// value after an iteration depends only on cells within three steps (its
+// domain's centre is one step away and that centre's decision reads two
+// further), so iteration j works on the centres at least 3j + 2 from the
+// window edge and the tile is exact after 7.  The iteration stays synchronous
+// inside one buffer: an accepted exchange of two unlike sites flips both, so
+// a deciding domain only sets bit 1 (flip) of its two bytes and every reader
+// looks at bit 0 (the value at the start of the iteration); after a barrier
+// one pass folds the flips into the values.  Domains are disjoint, so no byte
+// is marked twice.  Needs TW + 2 kMpkkHalo <= L and TR + 2 kMpkkHalo <= H.
+__global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                       uint32_t L, uint32_t H, uint32_t TW, uint32_t TR, uint32_t ntx,
+                                                       uint32_t k0, uint32_t k1, uint64_t t, TriAccept acc,
+                                                       unsigned long long* partials) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t win[];  // read as words by the flip pass
+  __shared__ uint32_t k_s[7], thr_s[11];
+  __shared__ uint32_t all_s;
+  __shared__ unsigned long long red[16];
+  const uint32_t N = L * H;
+  const uint32_t WC = TW + 2 * kMpkkHalo, WR = TR + 2 * kMpkkHalo, S = mpkk_window_stride(TW);
+  const uint32_t tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const uint32_t x0 = tx * TW, y0 = ty * TR;
+  const uint32_t TWe = min(TW, L - x0), TRe = min(TR, H - y0);
+  const uint32_t base =
+      (uint32_t)(((uint64_t)y0 * L + x0 + 2ull * N - (uint64_t)kMpkkHalo * L - kMpkkHalo) % (uint64_t)N);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t tl = (uint32_t)t;
+  if (threadIdx.x < 7) {
+    const uint32_t j = threadIdx.x;
+    const Philox4 b = philox10(j >> 2, 2u, tl, ctr_hi(t, kTagMpkkK), k0, k1);
+    const uint32_t w = (j & 3) == 0 ? b.x : (j & 3) == 1 ? b.y : (j & 3) == 2 ? b.z : b.w;
+    k_s[j] = (uint32_t)(((uint64_t)w * 7u) >> 32);
+  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + 11) {
+    const uint32_t n = threadIdx.x - 64;
+    const uint64_t T = acc.T[n];
+    thr_s[n] = T >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)T;
+    const uint32_t always = (uint32_t)__ballot(T >= 0x100000000ull);  // lanes 0..10 of wave 1
+    if (n == 0) all_s = always;
+  }
+  // the window, two rows per wave at a time, all loads of a batch issued first
+  for (uint32_t r0 = 2 * wave; r0 < WR; r0 += 2 * nwaves) {
+    for (uint32_t c0 = 0; c0 < WC; c0 += 512) {
+      uint8_t v[16];
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        // out-of-window lanes read the window's first site and drop it
+        const uint32_t r = r0 + (k >> 3), c = c0 + lane + 64u * (k & 7u);
+        const bool ok = r < WR && c < WC;
+        uint32_t rb = base + (ok ? r : 0u) * L;
+        rb = rb >= N ? rb - N : rb;
+        uint32_t i = rb + (ok ? c : 0u);
+        i = i >= N ? i - N : i;
+        v[k] = in[i];
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        const uint32_t r = r0 + (k >> 3), c = c0 + lane + 64u * (k & 7u);
+        if (r < WR && c < WC) win[r * S + c] = v[k];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t always = all_s;
+  const uint32_t th = ctr_hi(t, kTagMpkk);
+  const uint32_t lane_ring = lane * L, lane_win = lane * S;
+  const uint32_t wave_u = __builtin_amdgcn_readfirstlane(wave);
+  uint32_t* win32 = reinterpret_cast<uint32_t*>(win);
+  const uint32_t nwords = (S >> 2) * WR;
+  unsigned long long cnt = 0;
+  for (int j = 0; j < 7; ++j) {
+    const uint32_t k = k_s[j];
+    const uint32_t lo = 3u * (uint32_t)j + 2u;
+    const uint32_t rhi = WR - lo, chi = WC - lo;
+    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 6u) / 7u;
+    for (uint32_t it = wave_u; it < nrg * Q; it += nwaves) {
+      const uint32_t rg = it / Q, q = it - rg * Q;
+      const uint32_t r0 = lo + rg * 64u;
+      const uint32_t r = r0 + lane;
+      if (r >= rhi) continue;
+      uint32_t rb0 = base + r0 * L;
+      rb0 = rb0 >= N ? rb0 - N : rb0;
+      uint32_t rb = rb0 + lane_ring;
+      rb = rb >= N ? rb - N : rb;
+      const uint32_t c = lo + (k + 7u - (rb + lo) % 7u) % 7u + 7u * q;
+      if (c >= chi) continue;
+      uint32_t i = rb + c;
+      i = i >= N ? i - N : i;
+      const uint32_t m = (i - k) / 7u;  // the domain's index
+      const Philox4 rr = philox10(m >> 1, (uint32_t)j, tl, th, k0, k1);
+      const uint32_t wd = (m & 1u) ? rr.z : rr.x, u = (m & 1u) ? rr.w : rr.y;
+      const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
+      const uint32_t a = r0 * S + lane_win + c;
+      const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
+      const uint32_t b = (d & 1u) ? a - mag : a + mag;
+      // bit 0 of a byte is the value at the start of the iteration
+      const uint32_t va = win[a] & 1u, vb = win[b] & 1u;
+      if (va == vb) continue;
+      const uint32_t n = ((win[a + 1] ^ va) & 1u) + ((win[a - 1] ^ va) & 1u) + ((win[a + S] ^ va) & 1u) +
+                         ((win[a - S] ^ va) & 1u) + ((win[a + S - 1] ^ va) & 1u) + ((win[a - S + 1] ^ va) & 1u) +
+                         ((win[b + 1] ^ vb) & 1u) + ((win[b - 1] ^ vb) & 1u) + ((win[b + S] ^ vb) & 1u) +
+                         ((win[b - S] ^ vb) & 1u) + ((win[b + S - 1] ^ vb) & 1u) + ((win[b - S + 1] ^ vb) & 1u) - 2u;
+      if (u < thr_s[n] || ((always >> n) & 1u)) {
+        win[a] = (uint8_t)(va | 2u);
+        win[b] = (uint8_t)(vb | 2u);
+        cnt += (r - kMpkkHalo < TRe) & (c - kMpkkHalo < TWe);
+      }
+    }
+    __syncthreads();
+    // fold the flips: value ^= flip, four bytes at a time
+    for (uint32_t w = threadIdx.x; w < nwords; w += blockDim.x) {
+      const uint32_t x = win32[w];
+      win32[w] = (x & 0x01010101u) ^ ((x >> 1) & 0x01010101u);
+    }
+    __syncthreads();
+  }
+  // the tile
+  for (uint32_t r = kMpkkHalo + wave; r < kMpkkHalo + TRe; r += nwaves) {
+    uint32_t rb = base + r * L;
+    if (rb >= N) rb -= N;
+    for (uint32_t c = kMpkkHalo + lane; c < kMpkkHalo + TWe; c += 64) {
+      uint32_t i = rb + c;
+      if (i >= N) i -= N;
+      out[i] = win[r * S + c];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+  if (lane == 0) red[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (uint32_t w = 0; w < nwaves; ++w) tot += red[w];
+    if (tot) atomicAdd(&partials[blockIdx.x % kTriPartials], tot);
+  }
+}
+
 int tri_grid(size_t n) {
   const size_t g = (n + 255) / 256;
   return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
@@ -373,6 +511,16 @@ hipError_t launch_mpkk_iteration(const uint8_t* in, uint8_t* out, int L, int H, 
   const uint32_t N = (uint32_t)L * (uint32_t)H;
   hipLaunchKernelGGL(mpkk_iter, dim3(tri_grid(N / 7)), dim3(256), 0, stream, in, out, (uint32_t)L, N, k0, k1, t, j,
                      acc, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpkk_tile_step(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
+                                 uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
+                                 hipStream_t stream) {
+  if (!mpkk_tile_fits(L, H, TW, TR)) return hipErrorInvalidValue;
+  const uint32_t ntx = ((uint32_t)L + TW - 1) / TW, nty = ((uint32_t)H + TR - 1) / TR;
+  hipLaunchKernelGGL(mpkk_tile_step, dim3(ntx * nty), dim3(1024), mpkk_window_bytes(TW, TR), stream, in, out,
+                     (uint32_t)L, (uint32_t)H, (uint32_t)TW, (uint32_t)TR, ntx, k0, k1, t, acc, partials);
   return hipGetLastError();
 }
 

@@ -32,6 +32,22 @@ inline bool tri_tile_fits(int L, int H, int TW, int TR) {
 hipError_t launch_tri_tile_sweep(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
                                 uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
                                 hipStream_t stream);
+// Whole-step MPKK tiles (7 iterations per launch on an LDS window, `in` -> `out`).
+constexpr uint32_t kMpkkHalo = 21;  // 3 cells per iteration
+__host__ __device__ inline uint32_t mpkk_window_stride(uint32_t TW) {
+  const uint32_t s = (TW + 2 * kMpkkHalo + 3u) & ~3u;  // whole words, an odd number of them
+  return ((s >> 2) & 1u) ? s : s + 4u;
+}
+__host__ __device__ inline size_t mpkk_window_bytes(uint32_t TW, uint32_t TR) {
+  return (size_t)mpkk_window_stride(TW) * (TR + 2 * kMpkkHalo);
+}
+inline bool mpkk_tile_fits(int L, int H, int TW, int TR) {
+  return TW >= 16 && TR >= 16 && TW + 2 * (int)kMpkkHalo <= L && TR + 2 * (int)kMpkkHalo <= H &&
+         mpkk_window_bytes((uint32_t)TW, (uint32_t)TR) <= 160u * 1024u - 1024u;
+}
+hipError_t launch_mpkk_tile_step(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
+                                 uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
+                                 hipStream_t stream);
 hipError_t launch_mpkk_iteration(const uint8_t* in, uint8_t* out, int L, int H, uint32_t k0, uint32_t k1, uint64_t t,
                                  int j, const TriAccept& acc, unsigned long long* partials, hipStream_t stream);
 hipError_t launch_tri_energy(const uint8_t* lat, int L, int H, unsigned long long* out, hipStream_t stream);

@@ -97,3 +97,28 @@ def test_mpkk_full_size_4098x4095():
     assert int(got.sum()) == oracle.n_ones_rect(L, H, x)
     assert s.energy()[0] == oracle.tri_energy(got)
     s.close()
+
+
+@pytest.mark.parametrize("L,H,tile,x,w,n", [
+    (66, 70, (16, 16), 0.5, 0.8, 4), (80, 63, (30, 17), 0.45, 1.2, 5), (101, 84, (40, 20), 0.5, 0.5, 3),
+    (404, 420, (128, 96), 0.3, -0.6, 3), (234, 238, (192, 192), 0.5, 0.0, 2),
+])
+def test_mpkk_whole_step_tiles_match_oracle(L, H, tile, x, w, n):
+    # one launch per step on LDS windows (flip marks keep each iteration synchronous)
+    print(f"case mpkk tiles {L}x{H} tile={tile}", flush=True)
+    seed = wl.job_seed(63, L * 1000 + H)
+    s = kk.Sim(L, x, w, seed, geometry="triangular", rows=H, scheme="mpkk")
+    s.tri_set_tile(*tile)
+    assert s.tri_get_tile() == tile
+    ref = oracle.init_rect(L, H, x, seed)
+    acc = oracle.mpkk_steps(ref, w, seed, 0, n)
+    ms, launches = s.sweep_timed(n)
+    assert launches == n
+    assert np.array_equal(s.get_lattice(), ref)
+    assert s.stats() == (n, n * L * H, acc)
+    assert s.cluster_hist(0) == oracle.tri_cluster_hist(ref, 0)
+    s.tri_set_tile(0)       # back to one launch per iteration mid-run
+    s.sweep(2)
+    oracle.mpkk_steps(ref, w, seed, n, 2)
+    assert np.array_equal(s.get_lattice(), ref)
+    s.close()
