@@ -58,13 +58,17 @@ OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
 PROFILED_TRAFFIC = {"sources_sha256_prefix": "79d807e8d4da7bbd", "tile": (16, 128, 2),
-                    "bytes_per_launch": 10905061}
+                    "bytes_per_launch": 10905614}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
-TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "94560315aeefbcd3", "tile": (256, 256),
-                        "bytes_per_launch": 50472014}
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "e023065f53eb5e22", "tile": (256, 256),
+                        "bytes_per_launch": 50417420}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
+# And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
+# 192 x 192 tiles (profiles/mpkk_tile_step_4098x4095.md).
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "e023065f53eb5e22", "tile": (192, 192),
+                         "bytes_per_launch": 60424973}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
@@ -204,11 +208,15 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
     ops = MPKK_OPS_PER_ATTEMPT * per_launch / per_launch_s / 1e9
     hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
     sim.close()
+    traffic = None
+    if (kernel_sources_sha(TRI_KERNEL_SOURCES) == MPKK_PROFILED_TRAFFIC["sources_sha256_prefix"]
+            and tuple(mp_tile) == MPKK_PROFILED_TRAFFIC["tile"]):
+        traffic = MPKK_PROFILED_TRAFFIC["bytes_per_launch"]
     out = {"workload": f"literal MPKK, triangular helical {L}x{H} int8, x={x}, omega={w}, {steps} steps",
            "value": rate, "unit": "attempts/s",
            "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
                         "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
-                        "traffic": None, "kernel": "mpkk_tile_step" if mp_tile[0] else "mpkk_iter",
+                        "traffic": traffic, "kernel": "mpkk_tile_step" if mp_tile[0] else "mpkk_iter",
                         "kernel_us": round(per_launch_s * 1e6, 3),
                         "launches": int(launches), "ops_per_attempt": MPKK_OPS_PER_ATTEMPT,
                         "tile": {"cols": mp_tile[0], "rows": mp_tile[1]},

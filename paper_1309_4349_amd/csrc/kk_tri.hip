@@ -254,7 +254,8 @@ __global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict
       uint8_t v[16];
 #pragma unroll
       for (uint32_t k = 0; k < 16; ++k) {
-        // out-of-window lanes read site 0 and drop it: no branch around the load
+        // out-of-window lanes read the window's first site and drop it: no branch
+        // around the load
         const uint32_t r = r0 + (k >> 3), c = c0 + lane + 64u * (k & 7u);
         const bool ok = r < WR && c < WC;
         uint32_t rb = base + (ok ? r : 0u) * L;
