@@ -135,20 +135,34 @@ enum {
 kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t scheme, double composition,
                                   double omega_kT, uint64_t seed, void *hip_stream);
 
-/* Whole-sweep tiles of the triangular class schedule: with cols > 0 every sweep
- * is one launch whose workgroups each own a cols x rows tile and run all 16
- * classes on an LDS window of the ring around it (33 more sites on every
- * side, recomputed by each tile), writing the tile to the other lattice
- * buffer; cols == 0 selects one launch per class, in place.  Results do not
- * depend on the choice (the window carries every exchange that can reach the
- * tile within a sweep).  Needs cols, rows >= 16, cols + 66 <= L, rows + 66 <= H
- * and a window of at most 159 KiB ((cols + 66, rounded up to an odd number of
- * 4-byte words) x (rows + 66) bytes); KK_EINVAL otherwise and for other
- * schemes.  The default is the square tile (320, 256, 192, 160, 128, 96, 64,
- * 48, 32 or 16) of least modelled time, ceil(tiles / 256) x ((T + 32)^2 +
- * 4096), or 0 when none fits. */
+/* Whole-sweep tiles of a triangular handle.  Class schedule: with cols > 0
+ * every sweep is one launch whose workgroups each own a cols x rows tile and
+ * run all 16 classes on an LDS window of the ring around it (33 more sites on
+ * every side, recomputed by each tile), writing the tile to the other lattice
+ * buffer; cols == 0 selects one launch per class, in place.  Literal MPKK:
+ * with cols > 0 every step of 7 iterations is one launch on windows with 21
+ * more sites on every side; cols == 0 selects one launch per iteration.
+ * Results do not depend on the choice (the window carries every exchange that
+ * can reach the tile within the launch).  Needs cols, rows >= 16,
+ * cols + 2h <= L, rows + 2h <= H (h = 33, or 21 for MPKK) and a window of at
+ * most 159 KiB ((cols + 2h, rounded up to an odd number of 4-byte words) x
+ * (rows + 2h) bytes); KK_EINVAL otherwise and on square handles.  The default
+ * is the square tile (320, 256, 192, 160, 128, 96, 64, 48, 32 or 16) of least
+ * modelled time, ceil(tiles / 256) x ((T + h')^2 + 4096) with h' = 32 (21 for
+ * MPKK), or 0 when none fits. */
 kk_status kk_tri_set_tile(kk_sim *h, uint32_t cols, uint32_t rows);
 kk_status kk_tri_get_tile(kk_sim *h, uint32_t *cols, uint32_t *rows);
+
+/* Autotune the tile of a triangular handle (either scheme): time one launch
+ * per class (or per MPKK iteration) and every square tile of 320, 256, 192,
+ * 160, 128, 96, 64, 48, 32 and 16 that fits, over trial_sweeps sweeps (0 = 20)
+ * after two warm-up sweeps each, and keep the fastest on the handle.  The
+ * trials run on the handle's own buffers; its lattice, sweep counter and
+ * counters are restored exactly afterwards (results never depend on the tile).
+ * Outputs (any may be NULL): the chosen tile (0 x 0 = one launch per class or
+ * iteration) and its time per sweep in microseconds.  Blocking.  KK_EINVAL on
+ * a square handle (use kk_autotune). */
+kk_status kk_tri_autotune(kk_sim *h, uint32_t trial_sweeps, uint32_t *cols, uint32_t *rows, double *us_per_sweep);
 
 /* Sites per row and rows (H == L except for kk_create_triangular_ex). */
 kk_status kk_shape(kk_sim *h, uint32_t *L, uint32_t *H);

@@ -597,6 +597,75 @@ kk_status kk_tri_set_tile(kk_sim* h, uint32_t cols, uint32_t rows) {
   return KK_OK;
 }
 
+kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint32_t* rows, double* us_per_sweep) {
+  KK_GUARD(h);
+  if (h->geom == 0) return set_error(KK_EINVAL, "square lattice: use kk_autotune");
+  if (trial_sweeps == 0) trial_sweeps = 20;
+  if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
+  const bool mp = h->geom == 2;
+  // candidates: one launch per class / iteration, and every square tile that fits
+  std::vector<int> cands = {0};
+  for (int c : {320, 256, 192, 160, 128, 96, 64, 48, 32, 16})
+    if (mp ? mpkk_tile_fits(h->L, h->H, c, c) : tri_tile_fits(h->L, h->H, c, c)) cands.push_back(c);
+  // save the state; the trials run on the live buffers and everything is restored
+  uint64_t sw0 = 0, att0 = 0, acc0 = 0;
+  kk_status st = kk_stats(h, &sw0, &att0, &acc0);
+  if (st != KK_OK) return st;
+  const int cur0 = h->cur, tw0 = h->tri_tw, tr0 = h->tri_tr;
+  const size_t bytes = lattice_bytes(h);
+  void* save = nullptr;
+  st = dmalloc(h, &save, bytes);
+  if (st != KK_OK) return st;
+  auto restore = [&](int tw, int tr) -> kk_status {
+    h->tri_tw = tw;
+    h->tri_tr = tr;
+    hipError_t e = hipMemcpyAsync(h->lat[cur0], save, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->partials, 0, h->npartials * sizeof(unsigned long long), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(save);
+    if (e != hipSuccess) {
+      h->poisoned = true;
+      return set_error(KK_EDEVICE, "autotune restore: %s", hipGetErrorString(e));
+    }
+    h->cur = cur0;
+    h->t = sw0;
+    h->attempts = att0;
+    h->accepted_base = acc0;  // the partials were just zeroed
+    h->epoch += 1;
+    return KK_OK;
+  };
+  hipError_t e = hipMemcpyAsync(save, h->lat[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(save);
+    h->poisoned = true;
+    return set_error(KK_EDEVICE, "autotune save: %s", hipGetErrorString(e));
+  }
+  int best = tw0;
+  double best_us = 1e300;
+  for (int c : cands) {
+    h->tri_tw = h->tri_tr = c;
+    st = enqueue_sweeps(h, 2, nullptr, nullptr);  // warm-up
+    double ms = 0.0;
+    uint64_t nl = 0;
+    if (st == KK_OK) st = enqueue_sweeps(h, trial_sweeps, &ms, &nl);
+    if (st != KK_OK) {
+      (void)restore(tw0, tr0);
+      return st;
+    }
+    const double us = ms * 1e3 / trial_sweeps;
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  st = restore(best, best);
+  if (st != KK_OK) return st;
+  if (cols) *cols = (uint32_t)best;
+  if (rows) *rows = (uint32_t)best;
+  if (us_per_sweep) *us_per_sweep = best_us;
+  return KK_OK;
+}
+
 kk_status kk_tri_get_tile(kk_sim* h, uint32_t* cols, uint32_t* rows) {
   KK_GUARD(h);
   if (h->geom == 0) return set_error(KK_EINVAL, "tiles apply to triangular lattices only");

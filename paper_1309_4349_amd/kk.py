@@ -25,8 +25,7 @@ _STARTS = {"random": START_RANDOM, "segregated": START_SEGREGATED}
 
 EXPORTS = [
     "kk_create", "kk_create_ex", "kk_create_triangular", "kk_create_triangular_ex", "kk_shape", "kk_tri_thresholds",
-    "kk_tri_set_tile",
-    "kk_tri_get_tile",
+    "kk_tri_set_tile", "kk_tri_get_tile", "kk_tri_autotune",
     "kk_geometry", "kk_restart", "kk_sweep", "kk_sweep_async", "kk_sync", "kk_energy", "kk_cluster_hist",
     "kk_get_lattice", "kk_set_lattice", "kk_observe", "kk_sweep_series", "kk_stats", "kk_thresholds", "kk_info",
     "kk_set_tile", "kk_get_tile", "kk_autotune",
@@ -115,6 +114,7 @@ def load(path: str = LIB_PATH):
         "kk_shape": [P, u32p, u32p],
         "kk_tri_set_tile": [P, U32, U32],
         "kk_tri_get_tile": [P, u32p, u32p],
+        "kk_tri_autotune": [P, U32, u32p, u32p, dp],
         "kk_tri_thresholds": [P, u64p],
         "kk_geometry": [P, u32p],
         "kk_restart": [P, U32],
@@ -228,6 +228,12 @@ class Sim:
         a, b = ctypes.c_uint32(), ctypes.c_uint32()
         _check(load().kk_tri_get_tile(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def tri_autotune(self, trial_sweeps: int = 20) -> Tuple[int, int, float]:
+        """Time the triangular tiles and keep the fastest; returns (cols, rows, us_per_sweep)."""
+        a, b, us = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_double()
+        _check(load().kk_tri_autotune(self._h, trial_sweeps, ctypes.byref(a), ctypes.byref(b), ctypes.byref(us)))
+        return a.value, b.value, us.value
 
     def restart(self, start: str = "random"):
         """Back to a starting lattice ("random" or "segregated"), t = 0."""

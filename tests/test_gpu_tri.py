@@ -155,3 +155,23 @@ def test_tri_full_size_4092():
     assert np.array_equal(s.get_lattice(), b.get_lattice())
     s.close()
     b.close()
+
+
+@pytest.mark.parametrize("L,H,scheme", [(404, 404, "classes"), (404, 420, "mpkk"), (76, 84, "classes")])
+def test_tri_autotune_restores_state_and_keeps_results(L, H, scheme):
+    seed = wl.job_seed(44, L * 1000 + H)
+    s = kk.Sim(L, 0.5, 0.7, seed, geometry="triangular", rows=H, scheme=scheme)
+    s.sweep(3)
+    before = (s.get_lattice(), s.stats())
+    cols, rows, us = s.tri_autotune(4)
+    assert us > 0 and (cols, rows) == s.tri_get_tile()
+    assert np.array_equal(s.get_lattice(), before[0]) and s.stats() == before[1]
+    ref = oracle.init_rect(L, H, 0.5, seed)
+    run = oracle.tri_sweeps if scheme == "classes" else oracle.mpkk_steps
+    acc = run(ref, 0.7, seed, 0, 7)
+    s.sweep(4)
+    assert np.array_equal(s.get_lattice(), ref)
+    assert s.stats() == (7, 7 * L * H, acc)
+    s.close()
+    with pytest.raises(kk.KKError):
+        kk.Sim(64, 0.5, 0.7, 1).tri_autotune(2)
