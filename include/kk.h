@@ -305,10 +305,12 @@ typedef struct {
     double omega_kT;     /* interaction omega / kT, finite */
     uint64_t seed;       /* Philox key */
     uint64_t sweeps;     /* sweeps this replica makes on every kk_batch_run (at most 2^31 - 1) */
+    uint32_t start;      /* KK_START_RANDOM (0, kk_create's start) or KK_START_SEGREGATED */
 } kk_replica;
 
-/* Create n replicas (each placed as kk_create would) on one device; hip_stream
- * (NULL = own) carries the uploads and the tiled launches. */
+/* Create n replicas (each placed as kk_create would, then put at its start as
+ * kk_restart would) on one device; hip_stream (NULL = own) carries the uploads
+ * and the tiled launches.  KK_EINVAL for an unknown start. */
 kk_status kk_batch_create(kk_batch **out, const kk_replica *reps, size_t n, void *hip_stream);
 
 /* Advance every replica by its `sweeps` and wait. */

@@ -351,9 +351,15 @@ kk_status kk_batch_create(kk_batch** out, const kk_replica* reps, size_t n, void
   std::vector<uint64_t> sweeps;
   for (size_t i = 0; i < n; ++i) {
     kk_sim* h = nullptr;
+    if (reps[i].start != KK_START_RANDOM && reps[i].start != KK_START_SEGREGATED)
+      return fail(set_error(KK_EINVAL, "replica %zu: unknown start %u", i, reps[i].start));
     st = kk_create_ex(&h, reps[i].L, reps[i].composition, reps[i].omega_kT, reps[i].seed, reps[i].layout, b->sB);
     if (st != KK_OK) return fail(st);
     b->sims.push_back(h);  // owned from here on, also if planning fails
+    if (reps[i].start != KK_START_RANDOM) {
+      st = kk_restart(h, reps[i].start);
+      if (st != KK_OK) return fail(st);
+    }
     sims.push_back(h);
     sweeps.push_back(reps[i].sweeps);
   }

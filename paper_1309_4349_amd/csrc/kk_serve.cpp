@@ -124,6 +124,7 @@ void admit(kk_server* s) {
     j->t_admit = now_s(s);
     j->status = kk_create_ex(&j->sim, j->spec.L, j->spec.composition, j->spec.omega_kT, j->spec.seed,
                              j->spec.layout, s->stream);
+    if (j->status == KK_OK && j->spec.start != KK_START_RANDOM) j->status = kk_restart(j->sim, j->spec.start);
     if (j->status != KK_OK || j->spec.sweeps == 0) {
       retire(s, j);  // a job that cannot be placed (or has nothing to run) finishes at once
       continue;
@@ -196,6 +197,8 @@ kk_status kk_server_submit(kk_server* s, const kk_replica* job, double arrival_s
   if (job->layout == KK_LAYOUT_BITPACKED && job->L % 32 != 0)
     return set_error(KK_EINVAL, "bit-packed layout needs L %% 32 == 0 (got %u)", job->L);
   if (job->sweeps >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "too many sweeps");
+  if (job->start != KK_START_RANDOM && job->start != KK_START_SEGREGATED)
+    return set_error(KK_EINVAL, "unknown start %u", job->start);
   const size_t fp = job_footprint(*job, resolve_layout(*job));
   if (fp > s->cfg.hbm_budget_bytes)
     return set_error(KK_ENOMEM, "job needs %zu device bytes, budget is %llu", fp,

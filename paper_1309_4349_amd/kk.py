@@ -59,7 +59,8 @@ class Observables(ctypes.Structure):
 
 class Replica(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("composition", ctypes.c_double),
-                ("omega_kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64)]
+                ("omega_kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64),
+                ("start", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -348,14 +349,14 @@ class _Borrowed(Sim):
 
 class Batch:
     """Many replicas advanced together (kk_batch_*).  `jobs` are objects with
-    L, composition, omega, seed, sweeps and layout attributes."""
+    L, composition, omega, seed, sweeps and layout attributes, and optionally
+    start ("random" or "segregated")."""
 
     def __init__(self, jobs, stream: Optional[int] = None):
         lib = load()
         arr = (Replica * len(jobs))()
         for i, j in enumerate(jobs):
-            arr[i] = Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
-                             j.seed & (2**64 - 1), int(j.sweeps))
+            arr[i] = _replica(j)
         h = ctypes.c_void_p()
         _check(lib.kk_batch_create(ctypes.byref(h), arr, len(jobs), ctypes.c_void_p(stream) if stream else None))
         self._h = h
@@ -396,7 +397,7 @@ class Batch:
 
 def _replica(j) -> Replica:
     return Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
-                   j.seed & (2**64 - 1), int(j.sweeps))
+                   j.seed & (2**64 - 1), int(j.sweeps), _STARTS[getattr(j, "start", "random")])
 
 
 class Server:

@@ -46,6 +46,7 @@ class Job:
     hist_every: int = 0           # take a cluster histogram every k sweeps (0: only at the end)
     arrival: float = 0.0          # serving: arrival time in seconds from trace start
     tag: str = ""
+    start: str = "random"         # "random" or "segregated"
 
     @property
     def sites(self) -> int:

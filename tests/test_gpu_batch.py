@@ -2,6 +2,7 @@
 
 The batch mixes resident (whole lattice in LDS) and tiled replicas, int8 and
 bit-packed, positive, negative and zero omega, and uneven sweep counts."""
+import ctypes
 import sys
 
 import numpy as np
@@ -124,3 +125,25 @@ def test_batch_edge_cases_match_the_oracle(specs):
         assert s.stats() == (j.sweeps, j.sweeps * j.L * j.L, acc), (i, j.L)
         assert s.energy()[0] == oracle.energy(ref)
     b.close()
+
+
+def test_batch_segregated_starts_match_the_oracle():
+    # replicas may start segregated; each equals the oracle's segregated run
+    jobs = [wl.Job(L=64, composition=0.5, omega=0.7, seed=5, sweeps=30, layout="bitpacked", start="segregated"),
+            wl.Job(L=132, composition=0.3, omega=1.0, seed=6, sweeps=9, layout="int8", start="segregated"),
+            wl.Job(L=96, composition=0.6, omega=0.4, seed=7, sweeps=12, layout="int8"),
+            wl.Job(L=512, composition=0.5, omega=0.9, seed=8, sweeps=5, layout="bitpacked", start="segregated")]
+    b = kk.Batch(jobs)
+    b.run()
+    for i, j in enumerate(jobs):
+        say(f"  replica {i}: L={j.L} {j.layout} start={j.start}")
+        ref = oracle.init_segregated(j.L, j.composition) if j.start == "segregated" else \
+            oracle.init(j.L, j.composition, j.seed)
+        acc = oracle.sweeps(ref, j.omega, j.seed, 0, j.sweeps)
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), ref)
+        assert s.stats() == (j.sweeps, j.sweeps * j.L * j.L, acc)
+    b.close()
+    bad = (kk.Replica * 1)(kk.Replica(64, kk.LAYOUT_INT8, 0.5, 0.7, 5, 3, 7))
+    h = ctypes.c_void_p()
+    assert kk.load().kk_batch_create(ctypes.byref(h), bad, 1, None) == kk.KK_EINVAL

@@ -153,3 +153,17 @@ def test_replay_small_trace():
     assert out["jobs"] == 24 and out["failed"] == 0
     assert 0 < out["latency_p50_s"] <= out["latency_p99_s"]
     assert out["attempts"] == sum(j.L * j.L * j.sweeps for j in jobs)
+
+
+def test_server_segregated_job_matches_oracle():
+    j = wl.Job(L=64, composition=0.45, omega=0.8, seed=12345, sweeps=25, layout="int8", start="segregated")
+    srv = kk.Server(chunk_sweeps=10, keep_lattice=True)
+    jid = srv.submit(j)
+    while srv.step() != (0, 0):
+        pass
+    (r,) = srv.poll()
+    ref = oracle.init_segregated(j.L, j.composition)
+    acc = oracle.sweeps(ref, j.omega, j.seed, 0, j.sweeps)
+    assert np.array_equal(srv.job_lattice(jid), ref)
+    assert r["accepted"] == acc
+    srv.close()
