@@ -175,3 +175,31 @@ def test_tri_autotune_restores_state_and_keeps_results(L, H, scheme):
     s.close()
     with pytest.raises(kk.KKError):
         kk.Sim(64, 0.5, 0.7, 1).tri_autotune(2)
+
+
+def test_runner_series_and_resume(tmp_path):
+    import io
+    import json
+
+    from paper_1309_4349_amd import run
+    lat = tmp_path / "lat.npy"
+    hist = tmp_path / "hist.json"
+    buf = io.StringIO()
+    args = run.parse(["--geometry", "triangular", "--L", "100", "--x", "0.4", "--omega", "0.9", "--seed", "17",
+                      "--sweeps", "25", "--every", "10", "--start", "segregated", "--lattice-out", str(lat),
+                      "--hist-out", str(hist)])
+    recs = run.run(args, out=buf)
+    assert [r["sweep"] for r in recs] == [10, 20, 25]
+    assert [json.loads(x)["sweep"] for x in buf.getvalue().splitlines()] == [10, 20, 25]
+    ref = oracle.init_segregated(100, 0.4)
+    oracle.tri_sweeps(ref, 0.9, 17, 0, 25)
+    assert np.array_equal(np.load(lat), ref)
+    assert [tuple(e) for e in json.load(open(hist))] == oracle.tri_cluster_hist(ref, 1)
+    for k, v in oracle.tri_observables(ref, 0.9, 1, 17, 25).items():
+        assert recs[-1][k] == v
+    # resume for 5 more sweeps
+    recs2 = run.run(run.parse(["--geometry", "triangular", "--L", "100", "--x", "0.4", "--omega", "0.9", "--seed",
+                               "17", "--sweeps", "5", "--every", "5", "--resume", str(lat), "--resume-sweep", "25"]),
+                    out=io.StringIO())
+    oracle.tri_sweeps(ref, 0.9, 17, 25, 5)
+    assert recs2[-1]["sweep"] == 30 and recs2[-1]["n_unlike"] == oracle.tri_energy(ref)

@@ -67,3 +67,11 @@ def test_serving_summary_percentiles():
     assert out["latency_p50_s"] == pytest.approx(np.percentile([(i + 1) * 0.01 for i in range(100)], 50))
     assert out["latency_p99_s"] == pytest.approx(np.percentile([(i + 1) * 0.01 for i in range(100)], 99))
     assert out["attempts"] == 100 * 64 * 64 * 10
+
+
+def test_runner_arguments():
+    from paper_1309_4349_amd import run
+    a = run.parse(["--geometry", "square", "--L", "64", "--sweeps", "10", "--every", "5", "--start", "segregated"])
+    assert (a.geometry, a.L, a.sweeps, a.every, a.start, a.scheme) == ("square", 64, 10, 5, "segregated", "classes")
+    with pytest.raises(SystemExit):
+        run.parse(["--every", "0"])
