@@ -146,7 +146,10 @@ kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t
  * can reach the tile within the launch).  Needs cols, rows >= 16,
  * cols + 2h <= L, rows + 2h <= H (h = 33, or 21 for MPKK) and a window of at
  * most 159 KiB ((cols + 2h, rounded up to an odd number of 4-byte words) x
- * (rows + 2h) bytes); KK_EINVAL otherwise and on square handles.  The default
+ * (rows + 2h) bytes); KK_EINVAL otherwise and on square handles.  On the
+ * class schedule, cols = L and rows = H selects the whole ring in one
+ * workgroup's LDS (no halo, up to 1024 sweeps per launch, in place; needs
+ * L * H <= 159 KiB).  The default
  * is the square tile (320, 256, 192, 160, 128, 96, 64, 48, 32 or 16) of least
  * modelled time, ceil(tiles / 256) x ((T + h')^2 + 4096) with h' = 32 (21 for
  * MPKK), or 0 when none fits. */
@@ -160,7 +163,8 @@ kk_status kk_tri_get_tile(kk_sim *h, uint32_t *cols, uint32_t *rows);
  * trials run on the handle's own buffers; its lattice, sweep counter and
  * counters are restored exactly afterwards (results never depend on the tile).
  * Outputs (any may be NULL): the chosen tile (0 x 0 = one launch per class or
- * iteration) and its time per sweep in microseconds.  Blocking.  KK_EINVAL on
+ * iteration, L x H = the whole ring in one workgroup, also a candidate) and
+ * its time per sweep in microseconds.  Blocking.  KK_EINVAL on
  * a square handle (use kk_autotune). */
 kk_status kk_tri_autotune(kk_sim *h, uint32_t trial_sweeps, uint32_t *cols, uint32_t *rows, double *us_per_sweep);
 
@@ -363,6 +367,47 @@ void kk_batch_destroy(kk_batch *b);
  * needs (section "Results"), served together; this is the throughput side of
  * the method, not a step of it.
  * ------------------------------------------------------------------------- */
+/* ---- Batches of triangular lattices ----------------------------------
+ * Many replicas of the triangular helical lattice (the paper's model),
+ * advanced together.  When at least 64 class-schedule replicas have rings of
+ * at most 159 KiB, those run "resident": one launch per run, one workgroup per
+ * replica holding its whole ring in LDS for all of its sweeps.  Other
+ * class-schedule replicas whose lattice takes a whole-sweep tile are
+ * "batched": each sweep of a run is one launch whose workgroups are the tiles
+ * of all batched replicas that still have sweeps to make.  Literal-MPKK
+ * replicas and the rest run through their own launches on the batch stream.
+ * A replica's result equals what kk_create_triangular_ex + kk_restart(start)
+ * + kk_sweep(sweeps) per run gives alone (no replica index enters a random
+ * counter). */
+typedef struct kk_tri_batch kk_tri_batch;
+
+typedef struct {
+    uint32_t L;          /* sites per row, as for kk_create_triangular_ex */
+    uint32_t H;          /* rows */
+    uint32_t scheme;     /* KK_TRI_CLASSES or KK_TRI_MPKK */
+    uint32_t start;      /* KK_START_RANDOM or KK_START_SEGREGATED */
+    double composition;  /* fraction of type 1, in [0, 1] */
+    double omega_kT;     /* omega / kT, finite */
+    uint64_t seed;       /* Philox key */
+    uint64_t sweeps;     /* sweeps (MPKK: steps) of this replica on every kk_tri_batch_run, at most 2^31 - 1 */
+} kk_tri_replica;
+
+/* Create n replicas (validated and placed as kk_create_triangular_ex and
+ * kk_restart would) on one device; hip_stream (NULL = own) carries all of
+ * their work.  *out receives the batch (NULL on failure). */
+kk_status kk_tri_batch_create(kk_tri_batch **out, const kk_tri_replica *reps, size_t n, void *hip_stream);
+/* Advance every replica by its sweeps; blocking. */
+kk_status kk_tri_batch_run(kk_tri_batch *b);
+/* Borrow replica i's handle (owned by the batch: query it, copy its lattice,
+ * never destroy it). */
+kk_status kk_tri_batch_sim(kk_tri_batch *b, size_t i, kk_sim **sim_out);
+/* Resident replicas (whole ring in one workgroup), replicas in the batched
+ * tile launch, replicas run on their own, and tile jobs of the batched
+ * launch.  NULL outputs are skipped. */
+kk_status kk_tri_batch_info(kk_tri_batch *b, size_t *n_resident, size_t *n_batched, size_t *n_plain,
+                            size_t *n_jobs);
+void kk_tri_batch_destroy(kk_tri_batch *b);
+
 typedef struct kk_server kk_server;
 
 typedef struct {

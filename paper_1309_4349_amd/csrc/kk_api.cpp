@@ -348,10 +348,30 @@ kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* lau
   uint64_t nl = 0;
   const uint64_t sites = (uint64_t)h->L * (uint64_t)h->H;
   if (h->geom != 0) {
-    // triangular: one whole-sweep tile launch, or 16 launches (one per class)
-    // in place, per sweep; literal MPKK: 7 synchronous iterations per step
-    // between the two buffers
-    for (uint64_t k = 0; k < n; ++k) {
+    // triangular: the whole ring in one workgroup (many sweeps per launch, in
+    // place), one whole-sweep tile launch per sweep, or 16 launches (one per
+    // class) in place per sweep; literal MPKK: one whole-step tile launch or 7
+    // synchronous iterations per step between the two buffers
+    const bool whole = h->geom == 1 && h->tri_tw == h->L && h->tri_tr == h->H;
+    for (uint64_t left = whole ? n : 0; left > 0;) {
+      const uint64_t m = std::min<uint64_t>(left, kTriResidentChunk);
+      TriResidentRep R{};
+      R.lat = static_cast<uint8_t*>(h->lat[h->cur]);
+      R.L = (uint32_t)h->L;
+      R.H = (uint32_t)h->H;
+      R.sweeps = (uint32_t)m;
+      R.k0 = h->k0;
+      R.k1 = h->k1;
+      R.t0 = h->t;
+      R.acc = h->tacc;
+      R.partials = h->partials;
+      KK_HIP(launch_tri_resident_one(R, sites, h->stream));
+      nl += 1;
+      h->t += m;
+      h->attempts += m * sites;
+      left -= m;
+    }
+    for (uint64_t k = 0; k < (whole ? 0 : n); ++k) {
       if (h->geom == 1 && h->tri_tw > 0) {
         KK_HIP(launch_tri_tile_sweep(static_cast<const uint8_t*>(h->lat[h->cur]),
                                      static_cast<uint8_t*>(h->lat[h->cur ^ 1]), h->L, h->H, h->tri_tw, h->tri_tr,
@@ -585,6 +605,15 @@ kk_status kk_tri_set_tile(kk_sim* h, uint32_t cols, uint32_t rows) {
     return KK_OK;
   }
   const bool mp = h->geom == 2;
+  if (!mp && cols == (uint32_t)h->L && rows == (uint32_t)h->H) {
+    // the whole ring in one workgroup
+    if (!tri_resident_fits(h->L, h->H))
+      return set_error(KK_EINVAL, "the whole ring (%d bytes) does not fit one workgroup's LDS (%zu)", h->L * h->H,
+                       kTriResidentMaxBytes);
+    h->tri_tw = h->L;
+    h->tri_tr = h->H;
+    return KK_OK;
+  }
   const uint32_t halo = mp ? kMpkkHalo : kTriHalo;
   const bool fits = mp ? mpkk_tile_fits(h->L, h->H, (int)cols, (int)rows)
                         : tri_tile_fits(h->L, h->H, (int)cols, (int)rows);
@@ -604,7 +633,9 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
   if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
   const bool mp = h->geom == 2;
   // candidates: one launch per class / iteration, and every square tile that fits
+  // (-1: the whole ring in one workgroup)
   std::vector<int> cands = {0};
+  if (!mp && tri_resident_fits(h->L, h->H)) cands.push_back(-1);
   for (int c : {320, 256, 192, 160, 128, 96, 64, 48, 32, 16})
     if (mp ? mpkk_tile_fits(h->L, h->H, c, c) : tri_tile_fits(h->L, h->H, c, c)) cands.push_back(c);
   // save the state; the trials run on the live buffers and everything is restored
@@ -643,7 +674,8 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
   int best = tw0;
   double best_us = 1e300;
   for (int c : cands) {
-    h->tri_tw = h->tri_tr = c;
+    h->tri_tw = c < 0 ? h->L : c;
+    h->tri_tr = c < 0 ? h->H : c;
     st = enqueue_sweeps(h, 2, nullptr, nullptr);  // warm-up
     double ms = 0.0;
     uint64_t nl = 0;
@@ -658,10 +690,10 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
       best = c;
     }
   }
-  st = restore(best, best);
+  st = best < 0 ? restore(h->L, h->H) : restore(best, best);
   if (st != KK_OK) return st;
-  if (cols) *cols = (uint32_t)best;
-  if (rows) *rows = (uint32_t)best;
+  if (cols) *cols = (uint32_t)h->tri_tw;
+  if (rows) *rows = (uint32_t)h->tri_tr;
   if (us_per_sweep) *us_per_sweep = best_us;
   return KK_OK;
 }

@@ -58,7 +58,8 @@ struct kk_sim {
   int geom = 0;                          // 0 square torus; triangular helical int8 ring: 1 with the
                                          // conflict-free 16 classes, 2 with the literal MPKK cover
   kk::TriAccept tacc{};                  // triangular thresholds
-  int tri_tw = 0, tri_tr = 0;            // whole-sweep tile of the class schedule (0: one launch per class)
+  int tri_tw = 0, tri_tr = 0;            // whole-sweep tile of the class schedule (0: one launch per class;
+                                         // L x H: the whole ring in one workgroup)
   uint64_t epoch = 0;                    // bumped whenever the lattice may change
   uint64_t hist_epoch = ~(uint64_t)0;    // epoch and species of the cached histogram
   int hist_species = -1;

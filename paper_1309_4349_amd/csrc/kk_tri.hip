@@ -220,17 +220,17 @@ __global__ __launch_bounds__(256) void tri_similar(const uint8_t* s, uint32_t L,
 // The tile is then written to `out`.  Centres are counted as accepted only in
 // the tile, so every attempt of the sweep is counted once.  Needs the window
 // to fit the ring: TW + 2 kTriHalo <= L and TR + 2 kTriHalo <= H.
-__global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
-                                                       uint32_t L, uint32_t H, uint32_t TW, uint32_t TR, uint32_t ntx,
-                                                       uint32_t k0, uint32_t k1, uint64_t t, TriAccept acc,
-                                                       unsigned long long* partials) {
-  extern __shared__ uint8_t win[];
+// The work of one workgroup: tile (tx, ty) of TW x TR on the ring of H rows of
+// L sites, one sweep t from `in` to `out`; `win` is the dynamic LDS window.
+__device__ __forceinline__ void tri_tile_body(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, uint32_t L,
+                                              uint32_t H, uint32_t TW, uint32_t TR, uint32_t tx, uint32_t ty,
+                                              uint32_t k0, uint32_t k1, uint64_t t, const TriAccept& acc,
+                                              unsigned long long* partials, uint8_t* win) {
   __shared__ uint32_t perm_s[16], thr_s[11];
   __shared__ uint32_t all_s;
   __shared__ unsigned long long red[16];
   const uint32_t N = L * H;
   const uint32_t WC = TW + 2 * kTriHalo, WR = TR + 2 * kTriHalo, S = tri_window_stride(TW);
-  const uint32_t tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
   const uint32_t x0 = tx * TW, y0 = ty * TR;
   const uint32_t TWe = min(TW, L - x0), TRe = min(TR, H - y0);
   // ring index of window cell (0, 0)
@@ -342,6 +342,107 @@ __global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict
     for (uint32_t w = 0; w < nwaves; ++w) tot += red[w];
     if (tot) atomicAdd(&partials[blockIdx.x % kTriPartials], tot);
   }
+}
+
+__global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                       uint32_t L, uint32_t H, uint32_t TW, uint32_t TR, uint32_t ntx,
+                                                       uint32_t k0, uint32_t k1, uint64_t t, TriAccept acc,
+                                                       unsigned long long* partials) {
+  extern __shared__ uint8_t win[];
+  tri_tile_body(in, out, L, H, TW, TR, blockIdx.x % ntx, blockIdx.x / ntx, k0, k1, t, acc, partials, win);
+}
+
+// Many lattices in one launch: workgroup b does tile jobs[b].y of replica
+// jobs[b].x, sweep k of the run (buffers and sweep counter from the table).
+__global__ __launch_bounds__(1024) void tri_tile_sweep_batch(const TriBatchRep* reps, const uint2* jobs,
+                                                             uint32_t k) {
+  extern __shared__ uint8_t win[];
+  const uint2 jb = jobs[blockIdx.x];
+  const TriBatchRep& R = reps[jb.x];
+  const uint32_t par = R.cur ^ (k & 1u);
+  tri_tile_body(R.lat[par], R.lat[par ^ 1u], R.L, R.H, R.TW, R.TR, jb.y % R.ntx, jb.y / R.ntx, R.k0, R.k1,
+                R.t0 + k, R.acc, R.partials, win);
+}
+
+// ---------------------------------------------------------------------------
+// Small lattices: the whole ring of one replica in one workgroup's LDS (no
+// halo), all of its sweeps in one launch, written back in place.  The 16
+// classes of a sweep run in the sweep's order with a barrier between them;
+// neighbours wrap modulo N inside LDS.  Workgroup b runs replica b of the
+// table.
+__device__ __forceinline__ void tri_resident_body(const TriResidentRep& R, uint8_t* ring) {
+  __shared__ uint32_t perm_s[16], thr_s[11];
+  __shared__ uint32_t all_s;
+  __shared__ unsigned long long red[16];
+  const uint32_t L = R.L, N = R.L * R.H;
+  uint8_t* lat = R.lat;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + 11) {
+    const uint32_t n = threadIdx.x - 64;
+    const uint64_t T = R.acc.T[n];
+    thr_s[n] = T >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)T;
+    const uint32_t always = (uint32_t)__ballot(T >= 0x100000000ull);  // lanes 0..10 of wave 1
+    if (n == 0) all_s = always;
+  }
+  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) ring[i] = lat[i];
+  unsigned long long cnt = 0;
+  const uint32_t M = N >> 4;
+  for (uint32_t s = 0; s < R.sweeps; ++s) {
+    const uint64_t t = R.t0 + s;
+    __syncthreads();  // the previous sweep's last phase (and the load) are complete
+    if (threadIdx.x < 64) {
+      const uint32_t c = tri_order(R.k0, R.k1, t, (int)(threadIdx.x & 15u));
+      if (threadIdx.x < 16) perm_s[threadIdx.x] = c;
+    }
+    __syncthreads();
+    const uint32_t always = all_s;
+    const uint32_t tl = (uint32_t)t, th = ctr_hi(t, kTagTri);
+    for (int p = 0; p < 16; ++p) {
+      const uint32_t cls = perm_s[p];
+      for (uint32_t j = threadIdx.x; j < M; j += blockDim.x) {
+        const uint32_t i = cls + 16u * j;
+        const Philox4 r = philox10(i >> 1, 0u, tl, th, R.k0, R.k1);
+        const uint32_t wd = (i & 1u) ? r.z : r.x, u = (i & 1u) ? r.w : r.y;
+        const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
+        const uint32_t b = tri_nb(i, d, L, N);
+        const uint32_t vi = ring[i], vb = ring[b];
+        if (vi == vb) continue;
+        // the i-b bond is unlike and appears once in each neighbourhood
+        uint32_t n = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < 6; ++e) n += ring[tri_nb(i, e, L, N)] != vi;
+#pragma unroll
+        for (uint32_t e = 0; e < 6; ++e) n += ring[tri_nb(b, e, L, N)] != vb;
+        n -= 2u;
+        if (u < thr_s[n] || ((always >> n) & 1u)) {
+          ring[i] = (uint8_t)vb;
+          ring[b] = (uint8_t)vi;
+          ++cnt;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) lat[i] = ring[i];
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+  if (lane == 0) red[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (uint32_t w = 0; w < nwaves; ++w) tot += red[w];
+    if (tot) atomicAdd(&R.partials[0], tot);
+  }
+}
+
+__global__ __launch_bounds__(1024) void tri_resident(const TriResidentRep* reps) {
+  extern __shared__ uint8_t ring[];
+  tri_resident_body(reps[blockIdx.x], ring);
+}
+
+__global__ __launch_bounds__(1024) void tri_resident_one(TriResidentRep R) {
+  extern __shared__ uint8_t ring[];
+  tri_resident_body(R, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -512,6 +613,24 @@ hipError_t launch_mpkk_iteration(const uint8_t* in, uint8_t* out, int L, int H, 
   const uint32_t N = (uint32_t)L * (uint32_t)H;
   hipLaunchKernelGGL(mpkk_iter, dim3(tri_grid(N / 7)), dim3(256), 0, stream, in, out, (uint32_t)L, N, k0, k1, t, j,
                      acc, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_tile_sweep_batch(const TriBatchRep* reps, const uint2* jobs, uint32_t njobs, uint32_t k,
+                                       size_t lds_bytes, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(tri_tile_sweep_batch, dim3(njobs), dim3(1024), lds_bytes, stream, reps, jobs, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_resident(const TriResidentRep* reps, uint32_t nreps, size_t lds_bytes, hipStream_t stream) {
+  if (nreps == 0) return hipSuccess;
+  hipLaunchKernelGGL(tri_resident, dim3(nreps), dim3(1024), lds_bytes, stream, reps);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_resident_one(const TriResidentRep& rep, size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(tri_resident_one, dim3(1), dim3(1024), lds_bytes, stream, rep);
   return hipGetLastError();
 }
 

@@ -29,6 +29,38 @@ inline bool tri_tile_fits(int L, int H, int TW, int TR) {
   return TW >= 16 && TR >= 16 && TW + 2 * (int)kTriHalo <= L && TR + 2 * (int)kTriHalo <= H &&
          tri_window_bytes((uint32_t)TW, (uint32_t)TR) <= 160u * 1024u - 1024u;
 }
+// The whole ring in one workgroup's LDS (small lattices): N = L * H bytes.
+constexpr size_t kTriResidentMaxBytes = 160u * 1024u - 1024u;
+inline bool tri_resident_fits(int L, int H) {
+  return (size_t)L * (size_t)H <= kTriResidentMaxBytes;
+}
+struct TriResidentRep {
+  uint8_t* lat;  // the current buffer, updated in place
+  uint32_t L, H, sweeps;
+  uint32_t k0, k1;
+  uint64_t t0;
+  TriAccept acc;
+  unsigned long long* partials;
+};
+// Workgroup b runs replica b (reps[b].sweeps sweeps); lds_bytes = the largest N.
+hipError_t launch_tri_resident(const TriResidentRep* reps, uint32_t nreps, size_t lds_bytes, hipStream_t stream);
+// One replica, its descriptor passed by value.
+hipError_t launch_tri_resident_one(const TriResidentRep& rep, size_t lds_bytes, hipStream_t stream);
+constexpr uint64_t kTriResidentChunk = 1024;  // sweeps per launch of a single handle
+
+// One replica of a batched launch of whole-sweep tiles.  Sweep k of a run reads
+// lat[cur ^ (k & 1)] and writes the other buffer with sweep counter t0 + k.
+struct TriBatchRep {
+  uint8_t* lat[2];
+  uint32_t L, H, TW, TR, ntx, cur;
+  uint32_t k0, k1;
+  uint64_t t0;
+  TriAccept acc;
+  unsigned long long* partials;  // kTriPartials sums of the replica
+};
+// jobs[b] = (replica, tile) for workgroup b; lds_bytes = the largest window.
+hipError_t launch_tri_tile_sweep_batch(const TriBatchRep* reps, const uint2* jobs, uint32_t njobs, uint32_t k,
+                                       size_t lds_bytes, hipStream_t stream);
 hipError_t launch_tri_tile_sweep(const uint8_t* in, uint8_t* out, int L, int H, int TW, int TR, uint32_t k0,
                                 uint32_t k1, uint64_t t, const TriAccept& acc, unsigned long long* partials,
                                 hipStream_t stream);

@@ -31,6 +31,7 @@ EXPORTS = [
     "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
+    "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
     "kk_server_destroy",
@@ -61,6 +62,12 @@ class Replica(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("composition", ctypes.c_double),
                 ("omega_kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64),
                 ("start", ctypes.c_uint32)]
+
+
+class TriReplica(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("H", ctypes.c_uint32), ("scheme", ctypes.c_uint32),
+                ("start", ctypes.c_uint32), ("composition", ctypes.c_double), ("omega_kT", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -141,6 +148,10 @@ def load(path: str = LIB_PATH):
         "kk_batch_sim": [P, ctypes.c_size_t, PP],
         "kk_batch_info": [P, szp, szp, szp],
         "kk_batch_autotune": [P, U32, u32p, u32p, dp],
+        "kk_tri_batch_create": [PP, ctypes.POINTER(TriReplica), ctypes.c_size_t, P],
+        "kk_tri_batch_run": [P],
+        "kk_tri_batch_sim": [P, ctypes.c_size_t, PP],
+        "kk_tri_batch_info": [P, szp, szp, szp, szp],
         "kk_server_create": [PP, ctypes.POINTER(ServerConfig)],
         "kk_server_now": [P, dp],
         "kk_server_submit": [P, ctypes.POINTER(Replica), D, u64p],
@@ -159,6 +170,8 @@ def load(path: str = LIB_PATH):
     lib.kk_destroy.restype = None
     lib.kk_batch_destroy.argtypes = [P]
     lib.kk_batch_destroy.restype = None
+    lib.kk_tri_batch_destroy.argtypes = [P]
+    lib.kk_tri_batch_destroy.restype = None
     lib.kk_server_destroy.argtypes = [P]
     lib.kk_server_destroy.restype = None
     lib.kk_last_error.argtypes = []
@@ -334,12 +347,13 @@ class Sim:
 
 
 class _Borrowed(Sim):
-    """A replica handle owned by a Batch (never destroyed from Python)."""
+    """A replica handle owned by a Batch or TriBatch (never destroyed from Python)."""
 
-    def __init__(self, handle, L, omega, seed):
+    def __init__(self, handle, L, omega, seed, H=None, geometry="square"):
         self._h = handle
-        self.L = self.H = L
-        self.geometry = "square"
+        self.L = L
+        self.H = H or L
+        self.geometry = geometry
         self.omega = omega
         self.seed = seed
 
@@ -386,6 +400,49 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load().kk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TriBatch:
+    """Many triangular lattices advanced together (kk_tri_batch_*).  `jobs` are
+    objects with L, composition, omega, seed and sweeps attributes, and
+    optionally rows (default L), scheme ("classes" or "mpkk") and start."""
+
+    def __init__(self, jobs, stream: Optional[int] = None):
+        lib = load()
+        arr = (TriReplica * len(jobs))()
+        for i, j in enumerate(jobs):
+            arr[i] = TriReplica(j.L, getattr(j, "rows", 0) or j.L, _SCHEMES[getattr(j, "scheme", "classes")],
+                                _STARTS[getattr(j, "start", "random")], float(j.composition), float(j.omega),
+                                j.seed & (2**64 - 1), int(j.sweeps))
+        h = ctypes.c_void_p()
+        _check(lib.kk_tri_batch_create(ctypes.byref(h), arr, len(jobs), ctypes.c_void_p(stream) if stream else None))
+        self._h = h
+        self.jobs = list(jobs)
+
+    def run(self):
+        _check(load().kk_tri_batch_run(self._h))
+
+    def sim(self, i: int) -> Sim:
+        h = ctypes.c_void_p()
+        _check(load().kk_tri_batch_sim(self._h, i, ctypes.byref(h)))
+        j = self.jobs[i]
+        return _Borrowed(h, j.L, float(j.omega), j.seed, H=getattr(j, "rows", 0) or j.L, geometry="triangular")
+
+    def info(self):
+        r, a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().kk_tri_batch_info(self._h, ctypes.byref(r), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"resident": r.value, "batched": a.value, "plain": b.value, "tile_jobs": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().kk_tri_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

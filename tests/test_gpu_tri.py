@@ -203,3 +203,27 @@ def test_runner_series_and_resume(tmp_path):
                     out=io.StringIO())
     oracle.tri_sweeps(ref, 0.9, 17, 25, 5)
     assert recs2[-1]["sweep"] == 30 and recs2[-1]["n_unlike"] == oracle.tri_energy(ref)
+
+
+@pytest.mark.parametrize("L,H,x,w,n", [(100, 100, 0.5, 0.9, 12), (204, 204, 0.4, 0.6, 5), (300, 124, 0.5, -0.3, 4),
+                                       (28, 20, 0.5, 1.0, 1030), (12, 12, 0.5, 0.4, 3)])
+def test_tri_whole_ring_matches_oracle(L, H, x, w, n):
+    # the whole ring in one workgroup, up to 1024 sweeps per launch
+    print(f"case tri whole ring {L}x{H} n={n}", flush=True)
+    seed = wl.job_seed(45, L * 1000 + H)
+    s = kk.Sim(L, x, w, seed, geometry="triangular", rows=H)
+    s.tri_set_tile(L, H)
+    assert s.tri_get_tile() == (L, H)
+    ref = oracle.init_rect(L, H, x, seed)
+    acc = oracle.tri_sweeps(ref, w, seed, 0, n)
+    ms, launches = s.sweep_timed(n)
+    assert launches == (n + 1023) // 1024
+    assert np.array_equal(s.get_lattice(), ref)
+    assert s.stats() == (n, n * L * H, acc)
+    s.tri_set_tile(0)
+    s.sweep(2)
+    oracle.tri_sweeps(ref, w, seed, n, 2)
+    assert np.array_equal(s.get_lattice(), ref)
+    s.close()
+    with pytest.raises(kk.KKError):
+        kk.Sim(404, 0.5, 0.5, 1, geometry="triangular").tri_set_tile(404, 404)   # 163,216 B: too large
