@@ -152,7 +152,8 @@ kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t
  * L * H <= 159 KiB).  The default
  * is the square tile (320, 256, 192, 160, 128, 96, 64, 48, 32 or 16) of least
  * modelled time, ceil(tiles / 256) x ((T + h')^2 + 4096) with h' = 32 (21 for
- * MPKK), or 0 when none fits. */
+ * MPKK), or 0 when none fits; class-schedule rings of at most 12288 sites
+ * default to the whole ring. */
 kk_status kk_tri_set_tile(kk_sim *h, uint32_t cols, uint32_t rows);
 kk_status kk_tri_get_tile(kk_sim *h, uint32_t *cols, uint32_t *rows);
 

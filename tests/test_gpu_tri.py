@@ -120,8 +120,10 @@ def test_tri_default_tiles_and_rejections():
         with pytest.raises(kk.KKError):
             s.tri_set_tile(*bad)
     s.close()
-    assert kk.Sim(100, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() in ((16, 16), (32, 32))
-    assert kk.Sim(76, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() == (0, 0)   # 16 + 66 > 76
+    assert kk.Sim(100, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() == (100, 100)   # the whole ring
+    assert kk.Sim(148, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() == (16, 16)
+    assert kk.Sim(76, 0.5, 1.0, 1, geometry="triangular").tri_get_tile() == (76, 76)
+    assert kk.Sim(76, 0.5, 1.0, 1, geometry="triangular", rows=2400).tri_get_tile() == (0, 0)   # no tile fits
     m = kk.Sim(10, 0.5, 1.0, 1, geometry="triangular", rows=7, scheme="mpkk")
     with pytest.raises(kk.KKError):
         m.tri_set_tile(16, 16)

@@ -35,7 +35,9 @@ def test_tri_batch_equals_alone_and_oracle():
     print(f"case tri batch of {len(JOBS)}", flush=True)
     b = kk.TriBatch(JOBS)
     info = b.info()
-    assert info["resident"] == 0 and info["batched"] == 5 and info["plain"] == 2 and info["tile_jobs"] > 50
+    # fewer than 64 small rings: those whose default is the whole ring (100^2, 76^2, 124 x 84) and the
+    # MPKK replica run on their own; 204^2, 404 x 412 and 132 x 200 share the tile launches
+    assert (info["resident"], info["batched"], info["plain"]) == (0, 3, 4) and info["tile_jobs"] > 50
     b.run()
     b.run()   # the second run continues from the first
     for i, j in enumerate(JOBS):
