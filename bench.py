@@ -15,8 +15,9 @@ histogram of species 1.  The line also carries:
   * serving -- p50/p99 latency, served and offered attempts/s of the job
     server replaying the Poisson job trace, saturated and below saturation;
   * triangular -- the paper's own six-neighbour helical lattice (4092^2,
-    int8): attempts/s, the phase kernel's time per launch and its roofline,
-    with the triangular CPU oracle timed beside it;
+    int8): attempts/s, the tile kernel's time per launch and its roofline,
+    with the triangular CPU oracle timed beside it; and 256 replicas of the
+    paper's 100 x 100 lattice batched against one after another;
   * mpkk -- the paper's literal MPKK (7-site domain cover, synchronous
     iterations) on a 4098 x 4095 ring: attempts/s, roofline, oracle; and its
     bias: the equilibrium unlike-bond fraction against the exact conflict-free
@@ -119,7 +120,55 @@ def cpu_baseline(job, budget_s: float = 12.0):
 TRI_OPS_PER_ATTEMPT = 96.0
 
 
-def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
+def tri_batch(n: int, L: int, sweeps: int, n_plain: int):
+    """Many replicas of the paper's 100 x 100 triangular lattice in one batch
+    (each ring held whole in one workgroup), against the same replicas run one
+    after another through the single-lattice path."""
+    from dataclasses import dataclass
+
+    import torch
+
+    from paper_1309_4349_amd import kk
+
+    @dataclass
+    class Rep:
+        L: int
+        composition: float
+        omega: float
+        seed: int
+        sweeps: int
+
+    jobs = [Rep(L, 0.2 + 0.6 * (i % 7) / 6, 0.2 + 1.2 * (i % 13) / 12, 0x13094349 + i, sweeps) for i in range(n)]
+    b = kk.TriBatch(jobs)
+    info = b.info()
+    b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    rate = n * L * L * sweeps / dt
+    sims = [kk.Sim(j.L, j.composition, j.omega, j.seed, geometry="triangular") for j in jobs[:n_plain]]
+    for s_ in sims:
+        s_.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in sims:
+        s_.sweep(sweeps)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    for s_ in sims:
+        s_.close()
+    plain = n_plain * L * L * sweeps / dtp
+    log(f"[bench] triangular batch {n} x {L}^2: {rate:.3e} attempts/s, one after another {plain:.3e} "
+        f"({rate / plain:.1f}x) {info}")
+    return {"workload": f"{n} triangular {L}x{L} replicas, x in [0.2, 0.8], omega in [0.2, 1.4], {sweeps} sweeps each",
+            "batched_attempts_per_s": rate, "plain_attempts_per_s": plain, "plain_replicas_timed": n_plain,
+            "speedup": rate / plain, "layout": info}
+
+
+def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 1000):
     """Attempts/s of the triangular helical lattice (the paper's geometry)."""
     import torch
 
@@ -158,6 +207,7 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool):
                         "tile": {"cols": sim_tile[0], "rows": sim_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
     log(f"[bench] triangular {L}^2: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
+    out["batch"] = tri_batch(256, 100, batch_sweeps, 32)
     if cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         s = oracle.init(L, x, seed)
@@ -390,6 +440,7 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=500, help="sweeps timed per launch for the roofline")
     ap.add_argument("--no-tri", action="store_true", help="skip the triangular-lattice measurement")
     ap.add_argument("--tri-sweeps", type=int, default=500, help="sweeps of the 4092^2 triangular lattice")
+    ap.add_argument("--tri-batch-sweeps", type=int, default=1000, help="sweeps of each 100^2 replica in the batch")
     ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
     ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
     ap.add_argument("--mpkk-bias-steps", type=int, default=10000, help="measured steps per bias run")
@@ -493,7 +544,7 @@ def main():
 
     tri = None
     if not args.no_tri:
-        tri = triangular(args.tri_sweeps, 100, not args.no_cpu)
+        tri = triangular(args.tri_sweeps, 100, not args.no_cpu, args.tri_batch_sweeps)
 
     mp = None
     if not args.no_mpkk:
