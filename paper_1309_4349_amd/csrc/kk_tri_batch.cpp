@@ -40,6 +40,7 @@ struct kk_tri_batch {
   size_t res_lds = 0;            // largest resident ring
   TriResidentRep* d_res = nullptr;
   std::vector<size_t> order;     // tiled replicas, sweeps descending
+  std::vector<uint32_t> tw, tr;  // their tiles, fixed at creation (the job table depends on them)
   std::vector<size_t> plain;     // the others
   std::vector<size_t> job_end;   // jobs of order[0..i] = [0, job_end[i])
   size_t lds_bytes = 0;          // largest window of the batched replicas
@@ -131,6 +132,8 @@ kk_status kk_tri_batch_create(kk_tri_batch** out, const kk_tri_replica* reps, si
   std::vector<uint2> jobs;
   for (size_t k = 0; k < b->order.size(); ++k) {
     const kk_sim* h = b->sims[b->order[k]];
+    b->tw.push_back((uint32_t)h->tri_tw);
+    b->tr.push_back((uint32_t)h->tri_tr);
     const uint32_t ntx = (uint32_t)((h->L + h->tri_tw - 1) / h->tri_tw);
     const uint32_t nty = (uint32_t)((h->H + h->tri_tr - 1) / h->tri_tr);
     for (uint32_t t = 0; t < ntx * nty; ++t) jobs.push_back(make_uint2((uint32_t)k, t));
@@ -150,9 +153,24 @@ kk_status kk_tri_batch_create(kk_tri_batch** out, const kk_tri_replica* reps, si
   return KK_OK;
 }
 
+namespace {
+kk_status tri_batch_run(kk_tri_batch* b);
+}
+
 kk_status kk_tri_batch_run(kk_tri_batch* b) {
   if (!b) return set_error(KK_EINVAL, "NULL batch");
   if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  const kk_status st = tri_batch_run(b);
+  // a run that fails part way leaves the replicas' device and host state apart
+  if (st != KK_OK && b->poisoned)
+    for (kk_sim* h : b->sims) h->poisoned = true;
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+kk_status tri_batch_run(kk_tri_batch* b) {
   for (size_t i = 0; i < b->sims.size(); ++i) {
     const kk_sim* h = b->sims[i];
     if (h->poisoned) return set_error(KK_ESTATE, "replica %zu poisoned", i);
@@ -196,8 +214,9 @@ kk_status kk_tri_batch_run(kk_tri_batch* b) {
       R.lat[1] = static_cast<uint8_t*>(h->lat[1]);
       R.L = (uint32_t)h->L;
       R.H = (uint32_t)h->H;
-      R.TW = (uint32_t)h->tri_tw;
-      R.TR = (uint32_t)h->tri_tr;
+      // the tile of the job table, whatever the handle's own setting is now (results do not depend on it)
+      R.TW = b->tw[k];
+      R.TR = b->tr[k];
       R.ntx = (R.L + R.TW - 1) / R.TW;
       R.cur = (uint32_t)h->cur;
       R.k0 = h->k0;
@@ -235,6 +254,9 @@ kk_status kk_tri_batch_run(kk_tri_batch* b) {
   TB_HIP(hipStreamSynchronize(b->stream));
   return KK_OK;
 }
+}  // namespace
+
+extern "C" {
 
 kk_status kk_tri_batch_sim(kk_tri_batch* b, size_t i, kk_sim** sim_out) {
   if (!b || !sim_out) return set_error(KK_EINVAL, "NULL argument");

@@ -93,3 +93,21 @@ def test_tri_batch_resident_replicas():
             oracle.tri_sweeps(ref, j.omega, j.seed, 0, 2 * j.sweeps)
             assert np.array_equal(s.get_lattice(), ref), i
     b.close()
+
+
+def test_tri_batch_keeps_its_tiles_when_a_replica_changes_its_own():
+    # the batch's job table was built for each replica's tile at creation; a
+    # replica whose handle is re-tiled between runs still runs on that table
+    jobs = [TJ(404, 412, "classes", "random", 0.5, 0.7, 21, 4), TJ(204, 204, "classes", "random", 0.4, 0.9, 22, 3)]
+    b = kk.TriBatch(jobs)
+    b.run()
+    b.sim(0).tri_set_tile(96, 160)
+    b.sim(1).tri_set_tile(0)
+    b.run()
+    for i, j in enumerate(jobs):
+        ref = oracle.init_rect(j.L, j.rows, j.composition, j.seed)
+        acc = oracle.tri_sweeps(ref, j.omega, j.seed, 0, 2 * j.sweeps)
+        s = b.sim(i)
+        assert np.array_equal(s.get_lattice(), ref)
+        assert s.stats() == (2 * j.sweeps, 2 * j.sweeps * j.L * j.rows, acc)
+    b.close()
