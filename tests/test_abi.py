@@ -120,3 +120,21 @@ def test_null_handles_of_the_geometry_calls_are_rejected():
 def test_borrowed_batch_handles_describe_a_square_lattice():
     b = kk._Borrowed(None, 64, 0.5, 1)
     assert (b.L, b.H, b.geometry) == (64, 64, "square")
+
+
+def test_header_compiles_as_c99(tmp_path):
+    # the boundary is a C ABI: the header must stand alone in a C translation unit
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_kk.c"
+    src.write_text('#include "kk.h"\n'
+                   "int use(kk_sim *h, kk_tri_batch *b) {\n"
+                   "    kk_observables o; kk_tri_replica r; kk_replica q; (void)r; (void)q;\n"
+                   "    if (kk_tri_batch_run(b) != KK_OK) return 1;\n"
+                   "    return kk_observe(h, 1, &o) == KK_OK ? (int)KK_TRI_MPKK : (int)KK_START_SEGREGATED;\n"
+                   "}\n")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"), "-c",
+                    str(src), "-o", str(tmp_path / "use_kk.o")], check=True)
