@@ -96,7 +96,7 @@ def cpu_baseline(job, budget_s: float = 12.0):
 
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.set_threads(0)
     s = oracle.init(job.L, job.composition, job.seed)
     t0 = time.perf_counter()
     oracle.sweeps(s, job.omega, job.seed, 0, 1)
@@ -106,9 +106,18 @@ def cpu_baseline(job, budget_s: float = 12.0):
     oracle.sweeps(s, job.omega, job.seed, 1, n)
     dt = time.perf_counter() - t0
     rate = n * job.L * job.L / dt
+    # the same on one core, over a shorter sample
+    oracle.set_threads(1)
+    n1 = max(1, n // max(1, threads) // 2)
+    t0 = time.perf_counter()
+    oracle.sweeps(s, job.omega, job.seed, 1 + n, n1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} sweeps of the {job.L}x{job.L} x={job.composition} omega={job.omega} lattice "
-                      f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})"}
+                      f"({n * job.L * job.L:.3e} attempts, {dt:.1f} s, sweeps 1..{n})",
+            "single_core": {"value": n1 * job.L * job.L / dt1, "cores": 1,
+                            "sample": f"{n1} further sweeps ({dt1:.1f} s)"}}
 
 
 # Algorithmic cost of one attempt on the triangular lattice, in 32-bit VALU
@@ -209,7 +218,7 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 
     log(f"[bench] triangular {L}^2: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
     out["batch"] = tri_batch(256, 100, batch_sweeps, 32)
     if cpu:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = oracle.set_threads(0)
         s = oracle.init(L, x, seed)
         t0 = time.perf_counter()
         oracle.tri_sweeps(s, w, seed, 0, 1)

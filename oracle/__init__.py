@@ -65,6 +65,7 @@ def _load():
         "ko_cluster_counts": (U64, [u8p, U32, ctypes.c_int, u64p]),
         "ko_seq_kawasaki": (U64, [u8p, U32, D, U64, U64]),
         "ko_tri_seq_kawasaki": (U64, [u8p, U32, U32, D, U64, U64]),
+        "ko_set_threads": (ctypes.c_int, [ctypes.c_int]),
         "ko_mpkk_k": (ctypes.c_int, [U64, U64, ctypes.c_int]),
         "ko_mpkk_domain_randoms": (None, [U64, U64, ctypes.c_int, U64, u32p, u32p]),
         "ko_mpkk_iteration": (ctypes.c_int64, [u8p, U32, U32, ctypes.c_int, u32p, u32p, u64p]),
@@ -316,6 +317,11 @@ def tri_observables(s: np.ndarray, omega: float, species: int, seed: int, t: int
     N = s.shape[0] * s.shape[1]
     return _observables_of(tri_energy(s), 3 * N, tri_cluster_counts(s, species), tri_similar_sampled(s, seed, t),
                            N, omega)
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's per-class loops (n <= 0: unchanged); returns the count in force."""
+    return int(_load().ko_set_threads(int(n)))
 
 
 def init_segregated(L: int, composition: float, H: int = 0) -> np.ndarray:

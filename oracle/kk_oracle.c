@@ -993,3 +993,21 @@ out:
     free(u);
     return acc;
 }
+
+/* Threads of the OpenMP loops over the centres of one class (timing only: the
+ * result does not depend on it).  n <= 0 leaves the setting unchanged; returns
+ * the thread count now in force (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int ko_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
