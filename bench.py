@@ -106,11 +106,14 @@ def cpu_baseline(job, budget_s: float = 12.0):
     oracle.sweeps(s, job.omega, job.seed, 1, n)
     dt = time.perf_counter() - t0
     rate = n * job.L * job.L / dt
-    # the same on one core, over a shorter sample
+    # the same on one core, over about a third of the budget
     oracle.set_threads(1)
-    n1 = max(1, n // max(1, threads) // 2)
     t0 = time.perf_counter()
-    oracle.sweeps(s, job.omega, job.seed, 1 + n, n1)
+    oracle.sweeps(s, job.omega, job.seed, 1 + n, 1)
+    one1 = time.perf_counter() - t0
+    n1 = max(1, int(budget_s / 3 / max(one1, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.sweeps(s, job.omega, job.seed, 2 + n, n1)
     dt1 = time.perf_counter() - t0
     oracle.set_threads(threads)
     return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
