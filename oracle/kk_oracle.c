@@ -35,6 +35,17 @@
  * against Onsager's nearest-neighbour correlation; the sweep against an
  * independent sequential random-site Kawasaki chain; cluster histograms
  * against scipy's labelling with a periodic merge.
+ *
+ * Further sections (each with its own header below): the paper's own
+ * triangular lattice with helical boundaries (16 conflict-free classes,
+ * pinned by rolled recounts, brute-force conflict checks with failing
+ * controls, exact 4x4 Boltzmann, the two-particle binding law, random mixing
+ * and a Python BFS); the segregated start and a sequential random-site
+ * Kawasaki chain on the triangular lattice; and the paper's literal MPKK
+ * (7-site domain cover, synchronous domains), pinned by the cover partition,
+ * a hand-worked conflicting iteration, the lone-particle move rate and random
+ * mixing.  The relaxation of N_AB(t) against sequential Kawasaki is compared
+ * statistically only: beyond those error bars it is parity unpinned.
  */
 #include <math.h>
 #include <stdint.h>
