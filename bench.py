@@ -21,7 +21,7 @@ histogram of species 1.  The line also carries:
   * mpkk -- the paper's literal MPKK (7-site domain cover, synchronous
     iterations) on a 4098 x 4095 ring: attempts/s, roofline, oracle; and its
     bias: the equilibrium unlike-bond fraction against the exact conflict-free
-    chain on a 404 x 420 ring.
+    chain on a 1020 x 1036 ring, omega 0.1 .. 0.5.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -296,28 +296,34 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
         out["cpu_baseline"] = {"value": n * N / dtc, "unit": "attempts/s", "cores": 1, "kind": "oracle",
                                "sample": f"{n} steps of the same {L}x{H} ring ({dtc:.1f} s, single-threaded)"}
         log(f"[bench] mpkk oracle {n * N / dtc:.3e} attempts/s")
-    # bias: equilibrium N_AB / 3N, 404 x 420 ring, both schemes from the same start
+    # bias: equilibrium N_AB / 3N on a 1020 x 1036 ring (both schedules are defined on it), both
+    # schemes from the same random start; the drift between the two halves of the measured
+    # stretch shows whether the run was in equilibrium
     bias = []
-    L, H = 404, 420
+    L, H = 1020, 1036
     N = L * H
-    for omega in (0.3, 0.5):
+    for omega in (0.1, 0.2, 0.3, 0.4, 0.5):
         row = {"omega": omega}
         for scheme in ("classes", "mpkk"):
             sim = kk.Sim(L, 0.5, omega, 11, geometry="triangular", rows=H, scheme=scheme)
             sim.sweep(3000)
             v = []
-            for _ in range(bias_steps // 25):
-                sim.sweep(25)
+            for _ in range(bias_steps // 30):
+                sim.sweep(30)
                 v.append(sim.energy()[0] / (3 * N))
             sim.close()
-            b = np.array(v[: len(v) // 20 * 20]).reshape(20, -1).mean(1)
-            row[scheme] = {"f_unlike": float(b.mean()), "stderr": float(b.std(ddof=1) / math.sqrt(20))}
+            v = np.array(v[: len(v) // 20 * 20])
+            bm = v.reshape(20, -1).mean(1)
+            half = len(v) // 2
+            row[scheme] = {"f_unlike": float(bm.mean()), "stderr": float(bm.std(ddof=1) / math.sqrt(20)),
+                           "drift": float(v[half:].mean() - v[:half].mean())}
         row["mpkk_minus_exact"] = row["mpkk"]["f_unlike"] - row["classes"]["f_unlike"]
         row["sigma"] = row["mpkk_minus_exact"] / math.hypot(row["mpkk"]["stderr"], row["classes"]["stderr"])
-        log(f"[bench] mpkk bias at omega={omega}: {row['mpkk_minus_exact']:+.5f} ({row['sigma']:.1f} sigma)")
+        log(f"[bench] mpkk bias at omega={omega}: {row['mpkk_minus_exact']:+.5f} ({row['sigma']:.1f} sigma), "
+            f"drift {row['classes']['drift']:+.5f} / {row['mpkk']['drift']:+.5f}")
         bias.append(row)
     out["bias"] = {"workload": f"{L}x{H} ring, x=0.5, 3000 burn-in + {bias_steps} measured steps each, "
-                               "20 batch means", "rows": bias}
+                               "20 batch means; drift = second-half minus first-half mean", "rows": bias}
     return out
 
 
@@ -455,7 +461,7 @@ def main():
     ap.add_argument("--tri-batch-sweeps", type=int, default=1000, help="sweeps of each 100^2 replica in the batch")
     ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
     ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
-    ap.add_argument("--mpkk-bias-steps", type=int, default=10000, help="measured steps per bias run")
+    ap.add_argument("--mpkk-bias-steps", type=int, default=6000, help="measured steps per bias run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
