@@ -467,8 +467,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(replicas shard trivially across GPUs; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (independent replicas "
+              "would be spread over GPUs, one process each; one large lattice would be split into row "
+              "strips with a halo exchange per sweep)", file=sys.stderr)
         sys.exit(2)
 
     import torch
