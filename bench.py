@@ -296,6 +296,8 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
         out["cpu_baseline"] = {"value": n * N / dtc, "unit": "attempts/s", "cores": 1, "kind": "oracle",
                                "sample": f"{n} steps of the same {L}x{H} ring ({dtc:.1f} s, single-threaded)"}
         log(f"[bench] mpkk oracle {n * N / dtc:.3e} attempts/s")
+    if bias_steps <= 0:
+        return out
     # bias: equilibrium N_AB / 3N on a 1020 x 1036 ring (both schedules are defined on it), both
     # schemes from the same random start; the drift between the two halves of the measured
     # stretch shows whether the run was in equilibrium
@@ -461,7 +463,7 @@ def main():
     ap.add_argument("--tri-batch-sweeps", type=int, default=1000, help="sweeps of each 100^2 replica in the batch")
     ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
     ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
-    ap.add_argument("--mpkk-bias-steps", type=int, default=6000, help="measured steps per bias run")
+    ap.add_argument("--mpkk-bias-steps", type=int, default=6000, help="measured steps per bias run (0 skips the bias runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()

@@ -521,7 +521,12 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
     const uint32_t k = k_s[j];
     const uint32_t lo = 3u * (uint32_t)j + 2u;
     const uint32_t rhi = WR - lo, chi = WC - lo;
-    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 6u) / 7u;
+    // A work item is a lane's pair of consecutive domains m, m + 1 along its
+    // row (7 sites apart) with m even: both take their numbers from Philox
+    // block m/2, computed once.  The row's first pair may start one centre
+    // before the region; the ring end can break the pairing in one row of the
+    // window, where the second domain computes its own block.
+    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 26u) / 14u;
     for (uint32_t it = wave_u; it < nrg * Q; it += nwaves) {
       const uint32_t rg = it / Q, q = it - rg * Q;
       const uint32_t r0 = lo + rg * 64u;
@@ -531,29 +536,44 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
       rb0 = rb0 >= N ? rb0 - N : rb0;
       uint32_t rb = rb0 + lane_ring;
       rb = rb >= N ? rb - N : rb;
-      const uint32_t c = lo + (k + 7u - (rb + lo) % 7u) % 7u + 7u * q;
-      if (c >= chi) continue;
-      uint32_t i = rb + c;
-      i = i >= N ? i - N : i;
-      const uint32_t m = (i - k) / 7u;  // the domain's index
-      const Philox4 rr = philox10(m >> 1, (uint32_t)j, tl, th, k0, k1);
-      const uint32_t wd = (m & 1u) ? rr.z : rr.x, u = (m & 1u) ? rr.w : rr.y;
-      const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
-      const uint32_t a = r0 * S + lane_win + c;
-      const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
-      const uint32_t b = (d & 1u) ? a - mag : a + mag;
-      // bit 0 of a byte is the value at the start of the iteration
-      const uint32_t va = win[a] & 1u, vb = win[b] & 1u;
-      if (va == vb) continue;
-      const uint32_t n = ((win[a + 1] ^ va) & 1u) + ((win[a - 1] ^ va) & 1u) + ((win[a + S] ^ va) & 1u) +
-                         ((win[a - S] ^ va) & 1u) + ((win[a + S - 1] ^ va) & 1u) + ((win[a - S + 1] ^ va) & 1u) +
-                         ((win[b + 1] ^ vb) & 1u) + ((win[b - 1] ^ vb) & 1u) + ((win[b + S] ^ vb) & 1u) +
-                         ((win[b - S] ^ vb) & 1u) + ((win[b + S - 1] ^ vb) & 1u) + ((win[b - S + 1] ^ vb) & 1u) - 2u;
-      if (u < thr_s[n] || ((always >> n) & 1u)) {
-        win[a] = (uint8_t)(va | 2u);
-        win[b] = (uint8_t)(vb | 2u);
-        cnt += (r - kMpkkHalo < TRe) & (c - kMpkkHalo < TWe);
-      }
+      // the row's first centre in the region and its domain's index
+      const uint32_t cf = lo + (k + 7u - (rb + lo) % 7u) % 7u;
+      uint32_t i_f = rb + cf;
+      i_f = i_f >= N ? i_f - N : i_f;
+      const uint32_t mf = (i_f - k) / 7u;
+      // the item's second centre (never before cf) and first centre
+      const uint32_t c2 = cf + 7u * (1u - (mf & 1u)) + 14u * q;
+      const bool ok1 = c2 >= lo + 7u && c2 - 7u < chi, ok2 = c2 < chi;
+      if (!ok1 && !ok2) continue;
+      uint32_t i2 = rb + c2;
+      i2 = i2 >= N ? i2 - N : i2;
+      const uint32_t i1 = i2 >= 7u ? i2 - 7u : i2 + N - 7u;
+      const uint32_t m1 = (i1 - k) / 7u, m2 = (i2 - k) / 7u;
+      const Philox4 r1 = philox10(m1 >> 1, (uint32_t)j, tl, th, k0, k1);
+      Philox4 r2 = r1;
+      if ((m2 >> 1) != (m1 >> 1)) r2 = philox10(m2 >> 1, (uint32_t)j, tl, th, k0, k1);
+      const uint32_t rowa = r0 * S + lane_win;
+      // one domain: centre at column c, direction word wd, uniform u
+      auto attempt = [&](uint32_t c, uint32_t wd, uint32_t u) {
+        const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
+        const uint32_t a = rowa + c;
+        const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
+        const uint32_t b = (d & 1u) ? a - mag : a + mag;
+        // bit 0 of a byte is the value at the start of the iteration
+        const uint32_t va = win[a] & 1u, vb = win[b] & 1u;
+        if (va == vb) return;
+        const uint32_t n = ((win[a + 1] ^ va) & 1u) + ((win[a - 1] ^ va) & 1u) + ((win[a + S] ^ va) & 1u) +
+                           ((win[a - S] ^ va) & 1u) + ((win[a + S - 1] ^ va) & 1u) + ((win[a - S + 1] ^ va) & 1u) +
+                           ((win[b + 1] ^ vb) & 1u) + ((win[b - 1] ^ vb) & 1u) + ((win[b + S] ^ vb) & 1u) +
+                           ((win[b - S] ^ vb) & 1u) + ((win[b + S - 1] ^ vb) & 1u) + ((win[b - S + 1] ^ vb) & 1u) - 2u;
+        if (u < thr_s[n] || ((always >> n) & 1u)) {
+          win[a] = (uint8_t)(va | 2u);
+          win[b] = (uint8_t)(vb | 2u);
+          cnt += (r - kMpkkHalo < TRe) & (c - kMpkkHalo < TWe);
+        }
+      };
+      if (ok1) attempt(c2 - 7u, (m1 & 1u) ? r1.z : r1.x, (m1 & 1u) ? r1.w : r1.y);
+      if (ok2) attempt(c2, (m2 & 1u) ? r2.z : r2.x, (m2 & 1u) ? r2.w : r2.y);
     }
     __syncthreads();
     // fold the flips: value ^= flip, four bytes at a time

@@ -102,6 +102,8 @@ def test_mpkk_full_size_4098x4095():
 @pytest.mark.parametrize("L,H,tile,x,w,n", [
     (66, 70, (16, 16), 0.5, 0.8, 4), (80, 63, (30, 17), 0.45, 1.2, 5), (101, 84, (40, 20), 0.5, 0.5, 3),
     (404, 420, (128, 96), 0.3, -0.6, 3), (234, 238, (192, 192), 0.5, 0.0, 2),
+    # N/7 odd: the ring end breaks the pairing of consecutive domains in one window row
+    (59, 63, (17, 21), 0.5, 0.9, 4), (73, 77, (31, 35), 0.4, 1.0, 3), (409, 413, (96, 96), 0.5, 0.7, 3),
 ])
 def test_mpkk_whole_step_tiles_match_oracle(L, H, tile, x, w, n):
     # one launch per step on LDS windows (flip marks keep each iteration synchronous)
