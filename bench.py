@@ -63,13 +63,13 @@ PROFILED_TRAFFIC = {"sources_sha256_prefix": "79d807e8d4da7bbd", "tile": (16, 12
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
-TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "557aabfd69343382", "tile": (256, 256),
-                        "bytes_per_launch": 50450329}
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "5f51bb83efb42c66", "tile": (256, 256),
+                        "bytes_per_launch": 50444019}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 # And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
 # 192 x 192 tiles (profiles/mpkk_tile_step_4098x4095.md).
-MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "557aabfd69343382", "tile": (192, 192),
-                         "bytes_per_launch": 60420526}
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "5f51bb83efb42c66", "tile": (192, 192),
+                         "bytes_per_launch": 60453267}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
