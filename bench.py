@@ -58,18 +58,18 @@ OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
-PROFILED_TRAFFIC = {"sources_sha256_prefix": "79d807e8d4da7bbd", "tile": (16, 128, 2),
-                    "bytes_per_launch": 10905208}
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "9c62b97bbe2863ae", "tile": (16, 128, 2),
+                    "bytes_per_launch": 4772573}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
-TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "5f51bb83efb42c66", "tile": (256, 256),
-                        "bytes_per_launch": 50444019}
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (256, 256),
+                        "bytes_per_launch": 35855573}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 # And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
 # 192 x 192 tiles (profiles/mpkk_tile_step_4098x4095.md).
-MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "5f51bb83efb42c66", "tile": (192, 192),
-                         "bytes_per_launch": 60453267}
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (192, 192),
+                         "bytes_per_launch": 36468333}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:

@@ -89,4 +89,18 @@ struct Accept {
   uint32_t negmask;     // 0xFFFFFFFF when omega < 0
 };
 
+// Tile of workgroup b in a grid of n tiles numbered row by row.  Workgroups
+// are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod 8), and each
+// XCD has its own L2: this gives every XCD a contiguous run of tile numbers,
+// i.e. a band of tile rows, so that most of the rows a tile stages were written
+// through the same L2 by the previous launch.  A bijection on [0, n) for any
+// n; which workgroup sweeps a tile does not affect the result.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int kXcds = 8;
+  const int per = (n + kXcds - 1) / kXcds;  // tiles of each of the first `tall` XCDs
+  const int tall = n - (per - 1) * kXcds;   // 1..8 XCDs take `per` tiles, the rest per - 1
+  const int x = b % kXcds, l = b / kXcds;
+  return x < tall ? x * per + l : tall * per + (x - tall) * (per - 1) + l;
+}
+
 }  // namespace kk

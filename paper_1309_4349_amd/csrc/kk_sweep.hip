@@ -765,7 +765,7 @@ __device__ __forceinline__ void add_block_count(uint32_t* red_lds, unsigned coun
 template <int LAYOUT, int TWW, int KU>
 __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams p) {
   extern __shared__ uint32_t S[];
-  const unsigned count = halo_tile_sweep<LAYOUT, TWW, KU>(S, p, blockIdx.x);
+  const unsigned count = halo_tile_sweep<LAYOUT, TWW, KU>(S, p, xcd_tile((int)blockIdx.x, (int)gridDim.x));
   add_block_count(S + p.R * HaloGeom<TWW>::ST, count, p.accepted + blockIdx.x);
 }
 

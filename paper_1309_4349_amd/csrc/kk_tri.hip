@@ -349,7 +349,8 @@ __global__ __launch_bounds__(1024) void tri_tile_sweep(const uint8_t* __restrict
                                                        uint32_t k0, uint32_t k1, uint64_t t, TriAccept acc,
                                                        unsigned long long* partials) {
   extern __shared__ uint8_t win[];
-  tri_tile_body(in, out, L, H, TW, TR, blockIdx.x % ntx, blockIdx.x / ntx, k0, k1, t, acc, partials, win);
+  const uint32_t tile = (uint32_t)xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  tri_tile_body(in, out, L, H, TW, TR, tile % ntx, tile / ntx, k0, k1, t, acc, partials, win);
 }
 
 // Many lattices in one launch: workgroup b does tile jobs[b].y of replica
@@ -468,7 +469,8 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
   __shared__ unsigned long long red[16];
   const uint32_t N = L * H;
   const uint32_t WC = TW + 2 * kMpkkHalo, WR = TR + 2 * kMpkkHalo, S = mpkk_window_stride(TW);
-  const uint32_t tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const uint32_t tile = (uint32_t)xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const uint32_t tx = tile % ntx, ty = tile / ntx;
   const uint32_t x0 = tx * TW, y0 = ty * TR;
   const uint32_t TWe = min(TW, L - x0), TRe = min(TR, H - y0);
   const uint32_t base =
