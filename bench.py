@@ -67,9 +67,9 @@ TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (25
                         "bytes_per_launch": 35855573}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 # And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
-# 192 x 192 tiles (profiles/mpkk_tile_step_4098x4095.md).
-MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (192, 192),
-                         "bytes_per_launch": 36468333}
+# 257 x 256 tiles (profiles/mpkk_tile_step_4098x4095.md).
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (257, 256),
+                         "bytes_per_launch": 35114392}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
