@@ -481,14 +481,13 @@ void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr) {
       *tw = *tr = c;
     }
   }
-  if (!mpkk) return;
-  // MPKK: also the tiles that cut the ring into an nx x ny grid, so that the
-  // workgroups fill whole rounds of the 256 CUs (measured at 4098 x 4095: 16 x 16
+  // also the tiles that cut the ring into an nx x ny grid, so that the workgroups
+  // fill whole rounds of the 256 CUs (measured for MPKK at 4098 x 4095: 16 x 16
   // tiles of 257 x 256 take 123 us per step, 22 x 22 tiles of 192 take 157)
   for (int ny = 1; ny <= 64; ++ny) {
     for (int nx = 1; nx <= 64; ++nx) {
       const int cw = (L + nx - 1) / nx, cr = (H + ny - 1) / ny;
-      if (!mpkk_tile_fits(L, H, cw, cr)) continue;
+      if (!(mpkk ? mpkk_tile_fits(L, H, cw, cr) : tri_tile_fits(L, H, cw, cr))) continue;
       const double tiles = (double)((L + cw - 1) / cw) * (double)((H + cr - 1) / cr);
       const double cost = std::ceil(tiles / 256.0) * ((double)(cw + h) * (cr + h) + 4096.0);
       if (*tw == 0 || cost < best) {

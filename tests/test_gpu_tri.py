@@ -115,7 +115,7 @@ def test_tri_whole_sweep_tiles_match_oracle(L, H, tile, x, w, n):
 def test_tri_default_tiles_and_rejections():
     s = kk.Sim(4092, 0.5, 0.88, 5, geometry="triangular")
     assert s.tri_get_tile() == (256, 256)
-    assert kk.Sim(1028, 0.5, 0.88, 5, geometry="triangular").tri_get_tile() == (96, 96)
+    assert kk.Sim(1028, 0.5, 0.88, 5, geometry="triangular").tri_get_tile() == (61, 69)   # 17 x 15 tiles
     for bad in ((15, 64), (64, 15), (4092, 64), (400, 400)):
         with pytest.raises(kk.KKError):
             s.tri_set_tile(*bad)
