@@ -193,7 +193,9 @@ enum {
 kk_status kk_restart(kk_sim *h, uint32_t start);
 
 /* Run n_sweeps sweeps (N attempts each, the paper's MPKK step), t .. t+n-1,
- * and wait for them.  Advances the sweep counter. */
+ * and wait for them.  Advances the sweep counter.  The counter must stay a
+ * valid resume point: KK_EINVAL, with nothing run, when t + n_sweeps would
+ * reach 2^60 (also for kk_sweep_async, kk_sweep_timed and kk_sweep_series). */
 kk_status kk_sweep(kk_sim *h, uint64_t n_sweeps);
 
 /* Enqueue n_sweeps sweeps on the handle's stream and return without waiting.
@@ -244,8 +246,9 @@ kk_status kk_sweep_series(kk_sim *h, uint64_t every, uint64_t count, int species
 kk_status kk_get_lattice(kk_sim *h, uint8_t *host_out, size_t n);
 
 /* Replace the lattice with host_in (n == L*L bytes, each 0 or 1) and set the
- * sweep counter to sweep_t: together with kk_get_lattice this is an exact
- * checkpoint/resume, since every random number is addressed by (seed, t, site). */
+ * sweep counter to sweep_t (< 2^60, KK_EINVAL otherwise): together with
+ * kk_get_lattice this is an exact checkpoint/resume, since every random
+ * number is addressed by (seed, t, site). */
 kk_status kk_set_lattice(kk_sim *h, const uint8_t *host_in, size_t n, uint64_t sweep_t);
 
 /* Sweeps done (= the sweep counter t), attempts made (t' * L * L over the sweeps

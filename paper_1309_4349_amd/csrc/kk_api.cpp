@@ -337,6 +337,10 @@ struct EventPair {
 };
 
 kk_status enqueue_sweeps(kk_sim* h, uint64_t n, double* kernel_ms, uint64_t* launches) {
+  // the counter carries 60 bits (28 of them in the fourth Philox word); after
+  // the run it must still be a valid resume point, as kk_set_lattice requires
+  if (n >= ((uint64_t)1 << 60) || h->t + n >= ((uint64_t)1 << 60))
+    return set_error(KK_EINVAL, "sweep counter would reach 2^60");
   EventPair tm;
   if (kernel_ms) {
     *kernel_ms = 0.0;
@@ -917,6 +921,9 @@ kk_status kk_sweep_series(kk_sim* h, uint64_t every, uint64_t count, int species
   KK_GUARD(h);
   if (every == 0) return set_error(KK_EINVAL, "every must be at least 1");
   if (count > 0 && !out) return set_error(KK_EINVAL, "out is NULL");
+  const uint64_t lim = (uint64_t)1 << 60;
+  if (count > 0 && (every >= lim || count >= lim / every || h->t + every * count >= lim))
+    return set_error(KK_EINVAL, "sweep counter would reach 2^60");
   for (uint64_t i = 0; i < count; ++i) {
     kk_status st = kk_sweep(h, every);
     if (st == KK_OK) st = kk_observe(h, species, &out[i]);

@@ -206,17 +206,85 @@ def test_oracle_sweep_matches_shuffled_python_sweep(orc, L, omega):
         assert np.array_equal(a, b)
 
 
-def test_extension_word_decides_ties(orc):
-    # Force the tie branch: pick omega so that one threshold's top bits equal
-    # a site's prefix, and check the decision against the 42-bit comparison.
-    L, seed, t = 8, 99, 3
+def _omega_for_threshold(orc, n, target):
+    """A double omega with thresholds(omega)[n] == target exactly (dU = 6 - 2n > 0).
+
+    T[n] falls monotonically with omega, and between adjacent doubles near
+    omega ~ 1 it moves by far less than one unit, so bisection lands on every
+    integer in its range."""
+    lo, hi = 0.0, 64.0
+    assert int(orc.thresholds(lo)[n]) > target > int(orc.thresholds(hi)[n])
+    while True:
+        mid = 0.5 * (lo + hi)
+        assert lo < mid < hi, "target skipped between adjacent doubles"
+        v = int(orc.thresholds(mid)[n])
+        if v == target:
+            return mid
+        if v > target:
+            lo = mid
+        else:
+            hi = mid
+
+
+def _tie_site(orc, L, seed, t, s):
+    """A centre of the sweep's first class whose partner is unlike, with n <= 2
+    unlike outer neighbours (so T[n] < 2^42 is reachable) and a non-zero prefix."""
     r = orc.sweep_randoms(L, seed, t)
-    u10 = int(r[0, 0]) & 0x3FF
-    ext = orc.ext_word(seed, t, 0, 0)
-    U = (u10 << 32) | ext
-    assert U >> 32 == u10 and U & 0xFFFFFFFF == ext
-    # the tag separates the streams: ext differs from the sweep-field block word
-    assert ext != orc.philox4x32_10([0, 0, t, 1 << 28], [seed, 0])[0]
+    k0 = orc.phase_order(seed, t)[0]
+    for y in range(L):
+        for x in range(L):
+            if 2 * ((x - y) % 4) + (y % 2) != k0:
+                continue
+            d, u10 = int(r[y, x]) >> 10, int(r[y, x]) & 0x3FF
+            bx, by = [((x + 1) % L, y), ((x - 1) % L, y), (x, (y + 1) % L), (x, (y - 1) % L)][d]
+            if s[y, x] == s[by, bx] or u10 == 0:
+                continue
+            n = (6 - orc.local_dnab(s, x, y, d)) // 2
+            if n <= 2:
+                return x, y, n, u10
+    return None
+
+
+def test_extension_word_decides_ties(orc):
+    # Drive the oracle's sweep through the branch where the 10-bit prefix equals
+    # the threshold's top bits, so that the 32-bit extension word decides, and
+    # check the outcome against the 42-bit comparison U < T[n] of the contract
+    # (the Metropolis test of the paper's algorithm, with u = U / 2^42).  The
+    # first class of the sweep sees the starting lattice, so the tied site's n
+    # is known in advance; omega is then chosen to make T[n] land on
+    # u10 * 2^32 + lo for lo just below, at and just above the site's ext word.
+    L = 8
+    for seed in range(500, 600):
+        t = 3
+        s0 = orc.init(L, 0.5, seed)
+        found = _tie_site(orc, L, seed, t, s0)
+        if found is None:
+            continue
+        x, y, n, u10 = found
+        ext = orc.ext_word(seed, t, x, y)
+        if not 0 < ext < 0xFFFFFFFF:
+            continue
+        finals = {}
+        for name, lo, accept in (("ext", ext, False), ("ext+1", ext + 1, True), ("0", 0, False),
+                                 ("next prefix", 1 << 32, True)):
+            target = (u10 << 32) + lo
+            omega = _omega_for_threshold(orc, n, target)
+            assert int(orc.thresholds(omega)[n]) == target
+            assert (((u10 << 32) | ext) < target) == accept
+            a = s0.copy()
+            b = s0.copy()
+            acc_c = orc.sweeps(a, omega, seed, t, 1)
+            acc_p = _python_sweep(orc, b, omega, seed, t, np.random.default_rng(seed))
+            assert acc_c == acc_p, name
+            assert np.array_equal(a, b), name
+            finals[name] = a
+        # the tie really was decided by the extension word: rejecting and
+        # accepting the tied exchange lead to different lattices
+        assert not np.array_equal(finals["ext"], finals["ext+1"])
+        assert np.array_equal(finals["ext"], finals["0"])
+        assert np.array_equal(finals["ext+1"], finals["next prefix"])
+        return
+    pytest.fail("no lattice with a usable tied site")
 
 
 # --------------------------------------------------------------------------
@@ -382,6 +450,47 @@ def test_equilibrium_matches_sequential_kawasaki(orc, x, omega):
 
     (ma, sa), (mb, sb) = bm(fa), bm(fb)
     assert abs(ma - mb) < 5 * math.hypot(sa, sb), (ma, mb, sa, sb)
+
+
+@pytest.mark.parametrize("omega", [0.5, 1.2])
+def test_seq_kawasaki_4x4_samples_boltzmann(orc, omega):
+    # The sequential random-site chain is itself a Metropolis chain with a
+    # symmetric proposal, so on the 4 x 4 torus at half filling it must visit
+    # each of the 12870 states with probability exp(-omega N_AB) / Z, which the
+    # enumeration gives exactly (Materials and Methods, the Metropolis
+    # algorithm and the omega_AB equation).
+    states = orc.enumerate_states(4, 8).reshape(-1, 4, 4)
+    nab = np.array([_nab_numpy(s) for s in states])
+    index = {orc.lattice_hash(np.ascontiguousarray(s)): i for i, s in enumerate(states)}
+    w = np.exp(-omega * (nab - nab.min()))
+    pstate = w / w.sum()
+    levels = np.unique(nab)
+    s = orc.init(4, 0.5, 99)
+    orc.seq_kawasaki(s, omega, 98, 200)
+    M = 60_000
+    idx = np.empty(M, dtype=np.int64)
+    for k in range(M):
+        orc.seq_kawasaki(s, omega, 0x9E3779B9 * (k + 1), 1)
+        idx[k] = index[orc.lattice_hash(s)]
+    samples = nab[idx]
+    assert abs(_batch_means_z(samples, float((pstate * nab).sum()))) < 4.5
+    for m in levels:
+        p = float(pstate[nab == m].sum())
+        hits = int((samples == m).sum())
+        lam = p * M
+        if lam < 200:
+            assert hits <= lam + 6 * math.sqrt(lam) + 6, (m, p, hits)
+            continue
+        assert abs(_batch_means_z((samples == m).astype(float), p)) < 5.0, (m, p)
+    if omega < 1.0:
+        # state level: at omega = 1.2 the chain lingers in the striped ground
+        # states and successive samples are too correlated for a chi-square on
+        # counts; the batch-means level checks above cover that case
+        counts = np.bincount(idx, minlength=len(states))
+        expect = pstate * M
+        chi2 = float(((counts - expect) ** 2 / expect).sum())
+        dof = len(states) - 1
+        assert chi2 < dof + 6 * math.sqrt(2 * dof), chi2
 
 
 # --------------------------------------------------------------------------
