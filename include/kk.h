@@ -475,6 +475,32 @@ kk_status kk_server_get_stats(kk_server *s, kk_server_stats *out);
 /* Frees every job, queued, running or finished. */
 void kk_server_destroy(kk_server *s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweeps
+ * of kk_sweep on a square-torus lattice that the caller holds in device
+ * memory, with no allocation of any kind.
+ *   lattice   device pointer, in and out: KK_LAYOUT_INT8 (L*L bytes, 0/1,
+ *             row-major) or KK_LAYOUT_BITPACKED (L rows of L/32 uint32, bit b
+ *             of word g = site 32g + b); owned by the caller.
+ *   omega_kT, seed  as for kk_create; t0 = the first sweep's counter, so that
+ *             a handle at counter t0 holding the same lattice reaches the
+ *             same state with kk_sweep(n_sweeps), bit for bit.
+ *   accepted  device pointer (may be NULL): the accepted exchanges of these
+ *             sweeps are ADDED to *accepted.
+ *   hip_stream  the stream to enqueue on (NULL = the null stream).
+ * The call enqueues its work and returns without waiting.  The second lattice
+ * buffer and the per-tile counts live in a fixed device array of
+ * KK_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends: lattices up
+ * to 8 MiB (bit-packed L <= 8192, int8 L <= 2896) and at most 4096 sweep
+ * tiles; larger inputs give KK_EINVAL.  Every call on one GPU shares that
+ * array, so calls whose work overlaps on one GPU (other streams, other
+ * threads) race: serialise them.  KK_EINVAL also for a NULL lattice, a bad L
+ * or layout (L % 4 == 0; bit-packed L % 32 == 0), non-finite omega or
+ * t0 + n_sweeps >= 2^60; KK_EDEVICE for a failed launch. */
+#define KK_NOALLOC_SCRATCH_BYTES ((size_t)8 * 1048576 + (size_t)4096 * 8)
+kk_status kk_sweep_noalloc(void *lattice, uint32_t L, uint32_t layout, double omega_kT, uint64_t seed, uint64_t t0,
+                           uint64_t n_sweeps, unsigned long long *accepted, void *hip_stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *kk_last_error(void);
 

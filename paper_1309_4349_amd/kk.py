@@ -34,7 +34,7 @@ EXPORTS = [
     "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
-    "kk_server_destroy",
+    "kk_server_destroy", "kk_sweep_noalloc",
 ]
 
 
@@ -161,6 +161,7 @@ def load(path: str = LIB_PATH):
         "kk_server_job_lattice": [P, U64, P, ctypes.c_size_t],
         "kk_server_release": [P, U64],
         "kk_server_get_stats": [P, ctypes.POINTER(ServerStats)],
+        "kk_sweep_noalloc": [P, U32, U32, D, U64, U64, U64, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -183,6 +184,15 @@ def load(path: str = LIB_PATH):
 def _check(st: int):
     if st != KK_OK:
         raise KKError(st, load().kk_last_error().decode(errors="replace"))
+
+
+def sweep_noalloc(lattice_ptr: int, L: int, layout: str, omega: float, seed: int, t0: int, n: int,
+                  accepted_ptr: int = 0, stream: int = 0):
+    """kk_sweep_noalloc: n sweeps of a caller-held device lattice (device pointers as ints),
+    enqueued on `stream` without waiting; adds the accepted count into *accepted_ptr."""
+    _check(load().kk_sweep_noalloc(ctypes.c_void_p(lattice_ptr), L, _LAYOUTS[layout], float(omega),
+                                   seed & (2**64 - 1), t0, n, ctypes.c_void_p(accepted_ptr or None),
+                                   ctypes.c_void_p(stream or None)))
 
 
 class Sim:
