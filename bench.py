@@ -10,7 +10,8 @@ histogram of species 1.  The line also carries:
   * cpu_baseline -- the CPU oracle timed on a bounded sample of the same
     workload on this host;
   * batched -- aggregate attempts/s of the batch engine against the same
-    replicas run one after another through the plain path;
+    replicas run one after another through the plain path; batched_offgrid
+    -- the same with the int8 replicas' sides rounded to multiples of 4;
   * grid_400 -- the 12-run 400x400 grid batched, histograms every 1000 sweeps;
   * serving -- p50/p99 latency, served and offered attempts/s of the job
     server replaying the Poisson job trace, saturated and below saturation;
@@ -123,13 +124,80 @@ def cpu_baseline(job, budget_s: float = 12.0):
                             "sample": f"{n1} further sweeps ({dt1:.1f} s)"}}
 
 
+def classical_baseline(budget_s: float = 4.0):
+    """The paper's "classical computation": sequential random-site Kawasaki
+    (a random site, a random one of its 4 neighbours, Metropolis on the energy
+    recount) on one core, timed on the 4096^2 and one 400^2 workload."""
+    import oracle
+    from paper_1309_4349_amd import workloads as wl
+
+    out = {"kind": "oracle (sequential random-site Kawasaki)", "cores": 1, "unit": "attempts/s"}
+    for key, job in (("L4096", wl.big_4096()), ("L400", wl.grid_400()[5])):
+        s = oracle.init(job.L, job.composition, job.seed)
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            oracle.seq_kawasaki(s, job.omega, job.seed + n, 1)
+            n += 1
+        dt = time.perf_counter() - t0
+        out[key] = {"value": n * job.L * job.L / dt,
+                    "sample": f"{n} sweeps ({n * job.L * job.L:.3e} attempts, {dt:.1f} s) of {job.tag}"}
+        log(f"[bench] classical sequential Kawasaki {job.L}^2: {out[key]['value']:.3e} attempts/s on one core")
+    out["paper_context"] = ("the paper reports its GPU code (Tesla M2090, CUDA 4.1) up to about 55x faster than "
+                            "its sequential CPU computation (Xeon E5640, 2.67 GHz); different hardware, lattice "
+                            "and algorithm: context only")
+    return out
+
+
+def small_64(cpu: bool):
+    """The 64x64 workload (x = 0.5, omega = 0.5, 1000 sweeps, then N_AB and
+    the species-1 histogram): GPU seconds, and the oracle's CPU seconds on one
+    core for the same run."""
+    import torch
+
+    from paper_1309_4349_amd import kk
+    from paper_1309_4349_amd import workloads as wl
+
+    job = wl.small_64()
+    sim = kk.Sim(job.L, job.composition, job.omega, job.seed, layout=job.layout)
+    sim.sweep(2)
+    sim.restart()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(job.sweeps)
+    sim.energy()
+    sim.cluster_hist(1)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    sim.close()
+    out = {"workload": job.tag + ", then N_AB and the species-1 histogram", "gpu_s": gpu_s,
+           "gpu_attempts_per_s": job.attempts / gpu_s}
+    if cpu:
+        import oracle
+
+        threads = oracle.set_threads(1)
+        s = oracle.init(job.L, job.composition, job.seed)
+        t0 = time.perf_counter()
+        oracle.sweeps(s, job.omega, job.seed, 0, job.sweeps)
+        oracle.energy(s)
+        oracle.cluster_hist(s, 1)
+        out["oracle_cpu_s"] = time.perf_counter() - t0
+        out["oracle_cores"] = 1
+        oracle.set_threads(threads)
+    log(f"[bench] 64^2 config: GPU {gpu_s * 1e3:.2f} ms, oracle {out.get('oracle_cpu_s', float('nan')):.2f} s")
+    return out
+
+
 # Algorithmic cost of one attempt on the triangular lattice, in 32-bit VALU
-# lane-ops: one Philox4x32-10 block per centre (40, as above), the partner
-# direction and uniform (3), 12 neighbour addresses (2 each, 24), 12 unlike
-# tests and their sum (24), the threshold lookup and compare (3), the swap
-# (2) -> 96.  Algorithmic bytes: each site read and written once per sweep
-# (2 B).  The whole-sweep tile kernel recomputes a halo on top of this.
-TRI_OPS_PER_ATTEMPT = 96.0
+# lane-ops: one Philox4x32-10 block per two sites (20: a block's words 0-1
+# serve the even site of a pair and words 2-3 the odd one, so a kernel that
+# computes a whole block per centre does twice the method's random-number
+# work), the partner direction and uniform (3), 12 neighbour addresses (2
+# each, 24), 12 unlike tests and their sum (24), the threshold lookup and
+# compare (3), the swap (2) -> 76.  Algorithmic bytes: each site read and
+# written once per sweep (2 B).  The whole-sweep tile kernel recomputes a halo
+# on top of this.
+TRI_OPS_PER_ATTEMPT = 76.0
 
 
 def tri_batch(n: int, L: int, sweeps: int, n_plain: int):
@@ -329,15 +397,18 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
     return out
 
 
-def batched_vs_plain(sweeps: int, plain_sweeps: int):
+def batched_vs_plain(sweeps: int, plain_sweeps: int, offgrid: bool = False):
     """Aggregate attempts/s of the 256-replica table: one batch run against the
-    same replicas advanced one after another through the plain path."""
+    same replicas advanced one after another through the plain path.  With
+    `offgrid`, the int8 replicas keep sides that are multiples of 4 (most are
+    not whole 32-site words), so they run on the batch's tile kernel rather
+    than its whole-lattice resident kernels."""
     import torch
 
     from paper_1309_4349_amd import kk
     from paper_1309_4349_amd import workloads as wl
 
-    jobs = wl.batch_replicas(n=256, sweeps=sweeps)
+    jobs = wl.batch_replicas(n=256, sweeps=sweeps, offgrid=offgrid)
     sites = sum(j.L * j.L for j in jobs)
     b = kk.Batch(jobs)
     info = b.info()
@@ -367,7 +438,8 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int):
         f"{plain_rate:.3e} attempts/s")
     for s in sims:
         s.close()
-    return {"workload": "256 replicas, L log-uniform 64..1024 (multiples of 32), x~U[0.2,0.8], omega~U[0.2,1.4]",
+    rounding = ("int8 replicas multiples of 4, bit-packed multiples of 32" if offgrid else "multiples of 32")
+    return {"workload": f"256 replicas, L log-uniform 64..1024 ({rounding}), x~U[0.2,0.8], omega~U[0.2,1.4]",
             "sites": sites, "batched_sweeps": sweeps, "batched_attempts_per_s": batched_rate,
             "batched_s": tb, "plain_sweeps_per_replica": plain_sweeps, "plain_attempts_per_s": plain_rate,
             "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
@@ -551,9 +623,10 @@ def main():
     log(f"[bench] observables in {observe_ms:.2f} ms: {obs}")
     sim.close()
 
-    batched = None
+    batched = batched_off = None
     if not args.no_batch:
         batched = batched_vs_plain(args.batch_sweeps, args.batch_plain_sweeps)
+        batched_off = batched_vs_plain(args.batch_sweeps, args.batch_plain_sweeps, offgrid=True)
 
     grid = None
     if not args.no_batch:
@@ -571,11 +644,14 @@ def main():
     if not args.no_mpkk:
         mp = mpkk(args.mpkk_steps, args.mpkk_bias_steps, not args.no_cpu)
 
+    small = small_64(not args.no_cpu)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
         cpu = cpu_baseline(job)
         log(f"[bench] oracle {cpu['value']:.3e} attempts/s on {cpu['cores']} threads")
+        cpu["classical"] = classical_baseline()
 
     line = {
         "metric": "Kawasaki swap attempts/sec (4096^2 bit-packed lattice, omega=0.88, x=0.5)",
@@ -590,9 +666,11 @@ def main():
                         "similar_sampled": obs["similar_sampled"], "size_number_avg": obs["size_number_avg"],
                         "size_weight_avg": obs["size_weight_avg"]},
         "cpu_baseline": cpu,
+        "small_64": small,
     }
     if batched is not None:
         line["batched"] = batched
+        line["batched_offgrid"] = batched_off
     if grid is not None:
         line["grid_400"] = grid
     if served is not None:

@@ -149,18 +149,21 @@ kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t
  * (rows + 2h) bytes); KK_EINVAL otherwise and on square handles.  On the
  * class schedule, cols = L and rows = H selects the whole ring in one
  * workgroup's LDS (no halo, up to 1024 sweeps per launch, in place; needs
- * L * H <= 159 KiB).  The default
- * is the square tile (320, 256, 192, 160, 128, 96, 64, 48, 32 or 16) of least
- * modelled time, ceil(tiles / 256) x ((T + h')^2 + 4096) with h' = 32 (21 for
- * MPKK), or 0 when none fits; class-schedule rings of at most 12288 sites
- * default to the whole ring. */
+ * L * H <= 159 KiB).  The default is the tile of least modelled time,
+ * ceil(tiles / 256) x ((TW + h')(TR + h') + 4096) with h' = 32 (21 for MPKK),
+ * over the square tiles T x T (T = 320, 256, 192, 160, 128, 96, 64, 48, 32,
+ * 16) and the tiles that cut the ring into an nx x ny grid (TW = ceil(L/nx),
+ * TR = ceil(H/ny), nx, ny <= 64), or 0 when none fits; class-schedule rings
+ * of at most 12288 sites default to the whole ring. */
 kk_status kk_tri_set_tile(kk_sim *h, uint32_t cols, uint32_t rows);
 kk_status kk_tri_get_tile(kk_sim *h, uint32_t *cols, uint32_t *rows);
 
 /* Autotune the tile of a triangular handle (either scheme): time one launch
- * per class (or per MPKK iteration) and every square tile of 320, 256, 192,
- * 160, 128, 96, 64, 48, 32 and 16 that fits, over trial_sweeps sweeps (0 = 20)
- * after two warm-up sweeps each, and keep the fastest on the handle.  The
+ * per class (or per MPKK iteration), the handle's current tile, the default
+ * tile, every square tile of 320, 256, 192, 160, 128, 96, 64, 48, 32 and 16
+ * that fits and the four grid-cut tiles of least modelled time (see
+ * kk_tri_set_tile), over trial_sweeps sweeps (0 = 20) after two warm-up
+ * sweeps each, and keep the fastest on the handle.  The
  * trials run on the handle's own buffers; its lattice, sweep counter and
  * counters are restored exactly afterwards (results never depend on the tile).
  * Outputs (any may be NULL): the chosen tile (0 x 0 = one launch per class or
@@ -345,32 +348,6 @@ kk_status kk_batch_info(kk_batch *b, size_t *n_resident, size_t *n_tiled, size_t
 
 void kk_batch_destroy(kk_batch *b);
 
-/* ---------------------------------------------------------------------------
- * Job server: independent simulation jobs (a kk_replica each, `sweeps` being
- * the job's total) arrive at any time and are served on one device.
- *
- *  - Admission: jobs wait in arrival (FIFO) order until their device memory
- *    fits hbm_budget_bytes next to the jobs already admitted and a slot of
- *    max_active is free.  A job's charge is an upper bound of what it holds:
- *    two lattice buffers plus 8 bytes per site (placement keys, later the
- *    cluster labels) plus small tables.  A job that alone exceeds the budget
- *    is refused at submission (KK_ENOMEM).
- *  - Continuous batching: each kk_server_step advances every admitted job by
- *    min(chunk_sweeps, sweeps left) sweeps in one batch run (the batch engine
- *    above), retires the jobs that are done and admits waiting ones; jobs join
- *    and leave only between steps.
- *  - Results: for a finished job, N_AB and E/kT = omega * N_AB of the final
- *    lattice, the accepted-move count and the cluster-size histogram of
- *    species 1 (as kk_cluster_hist), plus the final lattice if keep_lattice
- *    is set.  Each equals what kk_create_ex + kk_sweep(sweeps) gives for the
- *    job alone, whatever else runs beside it.
- *  - Times are seconds on the server's monotonic clock (kk_server_now; zero at
- *    creation).  Latency = t_done - t_arrival.
- * The server is driven by one host thread; calls on one server must not
- * overlap.  Paper: the many short and long simulations its kinetic study
- * needs (section "Results"), served together; this is the throughput side of
- * the method, not a step of it.
- * ------------------------------------------------------------------------- */
 /* ---- Batches of triangular lattices ----------------------------------
  * Many replicas of the triangular helical lattice (the paper's model),
  * advanced together.  When at least 64 class-schedule replicas have rings of
@@ -412,6 +389,32 @@ kk_status kk_tri_batch_info(kk_tri_batch *b, size_t *n_resident, size_t *n_batch
                             size_t *n_jobs);
 void kk_tri_batch_destroy(kk_tri_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Job server: independent simulation jobs (a kk_replica each, `sweeps` being
+ * the job's total) arrive at any time and are served on one device.
+ *
+ *  - Admission: jobs wait in arrival (FIFO) order until their device memory
+ *    fits hbm_budget_bytes next to the jobs already admitted and a slot of
+ *    max_active is free.  A job's charge is an upper bound of what it holds:
+ *    two lattice buffers plus 8 bytes per site (placement keys, later the
+ *    cluster labels) plus small tables.  A job that alone exceeds the budget
+ *    is refused at submission (KK_ENOMEM).
+ *  - Continuous batching: each kk_server_step advances every admitted job by
+ *    min(chunk_sweeps, sweeps left) sweeps in one batch run (the batch engine
+ *    above), retires the jobs that are done and admits waiting ones; jobs join
+ *    and leave only between steps.
+ *  - Results: for a finished job, N_AB and E/kT = omega * N_AB of the final
+ *    lattice, the accepted-move count and the cluster-size histogram of
+ *    species 1 (as kk_cluster_hist), plus the final lattice if keep_lattice
+ *    is set.  Each equals what kk_create_ex + kk_sweep(sweeps) gives for the
+ *    job alone, whatever else runs beside it.
+ *  - Times are seconds on the server's monotonic clock (kk_server_now; zero at
+ *    creation).  Latency = t_done - t_arrival.
+ * The server is driven by one host thread; calls on one server must not
+ * overlap.  Paper: the many short and long simulations its kinetic study
+ * needs (section "Results"), served together; this is the throughput side of
+ * the method, not a step of it.
+ * ------------------------------------------------------------------------- */
 typedef struct kk_server kk_server;
 
 typedef struct {
@@ -446,6 +449,16 @@ kk_status kk_server_create(kk_server **out, const kk_server_config *cfg);
 
 /* Current time on the server clock. */
 kk_status kk_server_now(kk_server *s, double *t);
+
+/* The device bytes a job is charged at admission (an upper bound of what it
+ * holds at any time): two lattice buffers, the energy counters and one
+ * accepted-move sum per sweep tile, plus the larger of the placement scratch
+ * (8 bytes per site and the radix tables) and the retirement scratch (the
+ * cluster-labelling arrays, 8 bytes per site and the size tables, and with
+ * keep_lattice on a bit-packed job the N-byte unpack buffer of the lattice
+ * copy), plus 64 KiB for the job's share of the batch tables.  Host-only: no
+ * device call.  KK_EINVAL for a NULL argument, a bad L or layout. */
+kk_status kk_server_job_bytes(const kk_replica *job, uint32_t keep_lattice, uint64_t *bytes);
 
 /* Queue a job (validated as kk_create_ex would, plus the budget check).
  * arrival_s < 0 stamps the arrival now; otherwise it is taken as given (a

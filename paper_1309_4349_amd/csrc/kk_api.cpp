@@ -463,9 +463,36 @@ kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t 
 // ceil(tiles / 256) of those.  Pick the square tile of least modelled cost
 // (ties: the larger), or 0 -- one launch per class or iteration -- when no
 // tile fits.
-void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr) {
-  static const int cand[] = {320, 256, 192, 160, 128, 96, 64, 48, 32, 16};
+// Modelled time of a triangular / MPKK tile: rounds of 256 workgroups times the
+// mean window area a workgroup works per phase, plus a fixed cost per round.
+double tri_tile_cost(int L, int H, bool mpkk, int cw, int cr) {
   const int h = mpkk ? 21 : 32;
+  const double tiles = (double)((L + cw - 1) / cw) * (double)((H + cr - 1) / cr);
+  return std::ceil(tiles / 256.0) * ((double)(cw + h) * (cr + h) + 4096.0);
+}
+
+// The tiles that cut the ring into an nx x ny grid (nx, ny <= 64), so that the
+// workgroups fill whole rounds of the 256 CUs, in ascending modelled time
+// (measured for MPKK at 4098 x 4095: 16 x 16 tiles of 257 x 256 take 123 us
+// per step, 22 x 22 tiles of 192 take 157).
+std::vector<std::pair<int, int>> tri_grid_tiles(int L, int H, bool mpkk) {
+  std::vector<std::pair<double, std::pair<int, int>>> v;
+  for (int ny = 1; ny <= 64; ++ny)
+    for (int nx = 1; nx <= 64; ++nx) {
+      const int cw = (L + nx - 1) / nx, cr = (H + ny - 1) / ny;
+      if (!(mpkk ? mpkk_tile_fits(L, H, cw, cr) : tri_tile_fits(L, H, cw, cr))) continue;
+      v.push_back({tri_tile_cost(L, H, mpkk, cw, cr), {cw, cr}});
+    }
+  std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<std::pair<int, int>> out;
+  for (const auto& e : v)
+    if (std::find(out.begin(), out.end(), e.second) == out.end()) out.push_back(e.second);
+  return out;
+}
+
+const int kTriSquareTiles[] = {320, 256, 192, 160, 128, 96, 64, 48, 32, 16};
+
+void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr) {
   double best = 0.0;
   *tw = *tr = 0;
   // rings of up to 12288 sites: the whole ring in one workgroup (measured: 10 us
@@ -476,29 +503,20 @@ void tri_default_tile(int L, int H, bool mpkk, int* tw, int* tr) {
     *tr = H;
     return;
   }
-  for (int c : cand) {
+  for (int c : kTriSquareTiles) {
     if (!(mpkk ? mpkk_tile_fits(L, H, c, c) : tri_tile_fits(L, H, c, c))) continue;
-    const double tiles = (double)((L + c - 1) / c) * (double)((H + c - 1) / c);
-    const double cost = std::ceil(tiles / 256.0) * ((double)(c + h) * (c + h) + 4096.0);
+    const double cost = tri_tile_cost(L, H, mpkk, c, c);
     if (*tw == 0 || cost < best) {
       best = cost;
       *tw = *tr = c;
     }
   }
-  // also the tiles that cut the ring into an nx x ny grid, so that the workgroups
-  // fill whole rounds of the 256 CUs (measured for MPKK at 4098 x 4095: 16 x 16
-  // tiles of 257 x 256 take 123 us per step, 22 x 22 tiles of 192 take 157)
-  for (int ny = 1; ny <= 64; ++ny) {
-    for (int nx = 1; nx <= 64; ++nx) {
-      const int cw = (L + nx - 1) / nx, cr = (H + ny - 1) / ny;
-      if (!(mpkk ? mpkk_tile_fits(L, H, cw, cr) : tri_tile_fits(L, H, cw, cr))) continue;
-      const double tiles = (double)((L + cw - 1) / cw) * (double)((H + cr - 1) / cr);
-      const double cost = std::ceil(tiles / 256.0) * ((double)(cw + h) * (cr + h) + 4096.0);
-      if (*tw == 0 || cost < best) {
-        best = cost;
-        *tw = cw;
-        *tr = cr;
-      }
+  const auto grid = tri_grid_tiles(L, H, mpkk);
+  if (!grid.empty()) {
+    const double cost = tri_tile_cost(L, H, mpkk, grid[0].first, grid[0].second);
+    if (*tw == 0 || cost < best) {
+      *tw = grid[0].first;
+      *tr = grid[0].second;
     }
   }
 }
@@ -661,12 +679,22 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
   if (trial_sweeps == 0) trial_sweeps = 20;
   if (trial_sweeps > 100000) return set_error(KK_EINVAL, "trial_sweeps must be at most 100000");
   const bool mp = h->geom == 2;
-  // candidates: one launch per class / iteration, and every square tile that fits
-  // (-1: the whole ring in one workgroup)
-  std::vector<int> cands = {0};
-  if (!mp && tri_resident_fits(h->L, h->H)) cands.push_back(-1);
-  for (int c : {320, 256, 192, 160, 128, 96, 64, 48, 32, 16})
-    if (mp ? mpkk_tile_fits(h->L, h->H, c, c) : tri_tile_fits(h->L, h->H, c, c)) cands.push_back(c);
+  // candidates: one launch per class / iteration, the whole ring in one
+  // workgroup, the handle's current tile, the default pick, every square tile
+  // that fits and the four grid-cut tiles of least modelled time
+  std::vector<std::pair<int, int>> cands = {{0, 0}};
+  auto add = [&](int cw, int cr) {
+    if (std::find(cands.begin(), cands.end(), std::make_pair(cw, cr)) == cands.end()) cands.push_back({cw, cr});
+  };
+  if (!mp && tri_resident_fits(h->L, h->H)) add(h->L, h->H);
+  add(h->tri_tw, h->tri_tr);
+  int dw = 0, dr = 0;
+  tri_default_tile(h->L, h->H, mp, &dw, &dr);
+  add(dw, dr);
+  for (int c : kTriSquareTiles)
+    if (mp ? mpkk_tile_fits(h->L, h->H, c, c) : tri_tile_fits(h->L, h->H, c, c)) add(c, c);
+  const auto grid = tri_grid_tiles(h->L, h->H, mp);
+  for (size_t i = 0; i < grid.size() && i < 4; ++i) add(grid[i].first, grid[i].second);
   // save the state; the trials run on the live buffers and everything is restored
   uint64_t sw0 = 0, att0 = 0, acc0 = 0;
   kk_status st = kk_stats(h, &sw0, &att0, &acc0);
@@ -700,11 +728,11 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
     h->poisoned = true;
     return set_error(KK_EDEVICE, "autotune save: %s", hipGetErrorString(e));
   }
-  int best = tw0;
+  std::pair<int, int> best = {tw0, tr0};
   double best_us = 1e300;
-  for (int c : cands) {
-    h->tri_tw = c < 0 ? h->L : c;
-    h->tri_tr = c < 0 ? h->H : c;
+  for (const auto& c : cands) {
+    h->tri_tw = c.first;
+    h->tri_tr = c.second;
     st = enqueue_sweeps(h, 2, nullptr, nullptr);  // warm-up
     double ms = 0.0;
     uint64_t nl = 0;
@@ -719,7 +747,7 @@ kk_status kk_tri_autotune(kk_sim* h, uint32_t trial_sweeps, uint32_t* cols, uint
       best = c;
     }
   }
-  st = best < 0 ? restore(h->L, h->H) : restore(best, best);
+  st = restore(best.first, best.second);
   if (st != KK_OK) return st;
   if (cols) *cols = (uint32_t)h->tri_tw;
   if (rows) *rows = (uint32_t)h->tri_tr;

@@ -95,7 +95,7 @@ struct Accept {
 // i.e. a band of tile rows, so that most of the rows a tile stages were written
 // through the same L2 by the previous launch.  A bijection on [0, n) for any
 // n; which workgroup sweeps a tile does not affect the result.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
   constexpr int kXcds = 8;
   const int per = (n + kXcds - 1) / kXcds;  // tiles of each of the first `tall` XCDs
   const int tall = n - (per - 1) * kXcds;   // 1..8 XCDs take `per` tiles, the rest per - 1

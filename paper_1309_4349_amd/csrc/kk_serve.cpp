@@ -61,18 +61,33 @@ namespace {
 
 double now_s(const kk_server* s) { return std::chrono::duration<double>(Clock::now() - s->t0).count(); }
 
-// Upper bound of the device bytes a job holds at any time: two lattice buffers,
-// plus the larger of the placement keys and the cluster-labelling arrays
-// (8 bytes per site either way), plus small tables.
-size_t job_footprint(const kk_replica& r, int layout) {
-  const size_t N = (size_t)r.L * r.L;
-  const size_t lat = layout == KK_LAYOUT_BITPACKED ? N / 8 : N;
-  return 2 * lat + 8 * N + 4 * (N / 4096 + 1) + (64u << 10);
-}
-
 int resolve_layout(const kk_replica& r) {
   if (r.layout == KK_LAYOUT_AUTO) return r.L % 32 == 0 ? KK_LAYOUT_BITPACKED : KK_LAYOUT_INT8;
   return (int)r.layout;
+}
+
+// Upper bound of the device bytes a job's handle holds at any time.  Always:
+// two lattice buffers, the energy counters and one accepted-move sum per
+// sweep tile.  On top, the larger of the two phases that need scratch:
+// placement (8-byte keys per site and the radix tables, freed after it) and
+// retirement (the cluster-labelling arrays, 8 bytes per site plus the size
+// tables, and for a bit-packed lattice kept on the host the N-byte unpack
+// buffer of kk_get_lattice, taken while the labelling arrays are still held).
+// 64 KiB of slack covers the job's share of the batch tables.
+size_t job_footprint(const kk_replica& r, bool keep_lattice) {
+  const int layout = resolve_layout(r);
+  const size_t N = (size_t)r.L * r.L;
+  const size_t lat = layout == KK_LAYOUT_BITPACKED ? N / 8 : N;
+  TileConfig tc;
+  kk::default_tile((int)r.L, layout == KK_LAYOUT_BITPACKED ? kk::kLayoutBits : kk::kLayoutInt8, &tc);
+  SweepParams p{};
+  kk::tile_geometry((int)r.L, tc, &p);
+  const size_t tiles = (size_t)p.tiles_x * (size_t)(((int)r.L + p.th - 1) / p.th);
+  const size_t base = 2 * lat + 2 * sizeof(unsigned long long) + tiles * sizeof(unsigned long long);
+  const size_t placement = 8 * N + (256 + 1 + 4096) * sizeof(unsigned);
+  const size_t labelling = 8 * N + kk::kSmallSizes * sizeof(unsigned) + 4 * (N / 4096 + 1) + sizeof(unsigned) +
+                           ((keep_lattice && layout == KK_LAYOUT_BITPACKED) ? N : 0);
+  return base + std::max(placement, labelling) + (64u << 10);
 }
 
 void destroy_job(Job* j) {
@@ -179,6 +194,17 @@ kk_status kk_server_create(kk_server** out, const kk_server_config* cfg) {
   return KK_OK;
 }
 
+kk_status kk_server_job_bytes(const kk_replica* job, uint32_t keep_lattice, uint64_t* bytes) {
+  if (!job || !bytes) return set_error(KK_EINVAL, "NULL argument");
+  if (job->L < 4 || job->L % 4 != 0 || job->L > 32768)
+    return set_error(KK_EINVAL, "L must be a multiple of 4 in [4, 32768] (got %u)", job->L);
+  if (job->layout > KK_LAYOUT_BITPACKED) return set_error(KK_EINVAL, "unknown layout %u", job->layout);
+  if (job->layout == KK_LAYOUT_BITPACKED && job->L % 32 != 0)
+    return set_error(KK_EINVAL, "bit-packed layout needs L %% 32 == 0 (got %u)", job->L);
+  *bytes = job_footprint(*job, keep_lattice != 0);
+  return KK_OK;
+}
+
 kk_status kk_server_now(kk_server* s, double* t) {
   if (!s || !t) return set_error(KK_EINVAL, "NULL argument");
   *t = now_s(s);
@@ -199,7 +225,7 @@ kk_status kk_server_submit(kk_server* s, const kk_replica* job, double arrival_s
   if (job->sweeps >= ((uint64_t)1 << 60)) return set_error(KK_EINVAL, "too many sweeps");
   if (job->start != KK_START_RANDOM && job->start != KK_START_SEGREGATED)
     return set_error(KK_EINVAL, "unknown start %u", job->start);
-  const size_t fp = job_footprint(*job, resolve_layout(*job));
+  const size_t fp = job_footprint(*job, s->cfg.keep_lattice != 0);
   if (fp > s->cfg.hbm_budget_bytes)
     return set_error(KK_ENOMEM, "job needs %zu device bytes, budget is %llu", fp,
                      (unsigned long long)s->cfg.hbm_budget_bytes);

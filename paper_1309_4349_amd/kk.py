@@ -34,7 +34,7 @@ EXPORTS = [
     "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
-    "kk_server_destroy", "kk_sweep_noalloc",
+    "kk_server_destroy", "kk_server_job_bytes", "kk_sweep_noalloc",
 ]
 
 
@@ -162,6 +162,7 @@ def load(path: str = LIB_PATH):
         "kk_server_release": [P, U64],
         "kk_server_get_stats": [P, ctypes.POINTER(ServerStats)],
         "kk_sweep_noalloc": [P, U32, U32, D, U64, U64, U64, P, P],
+        "kk_server_job_bytes": [ctypes.POINTER(Replica), U32, u64p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -465,6 +466,14 @@ class TriBatch:
 def _replica(j) -> Replica:
     return Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
                    j.seed & (2**64 - 1), int(j.sweeps), _STARTS[getattr(j, "start", "random")])
+
+
+def server_job_bytes(job, keep_lattice: bool = False) -> int:
+    """kk_server_job_bytes: the device bytes the job server charges a job at admission."""
+    out = ctypes.c_uint64()
+    r = _replica(job)
+    _check(load().kk_server_job_bytes(ctypes.byref(r), 1 if keep_lattice else 0, ctypes.byref(out)))
+    return out.value
 
 
 class Server:

@@ -84,17 +84,21 @@ def big_4096(sweeps: int = 10_000) -> Job:
                layout="bitpacked", tag="4096x4096 bitpacked x=0.5 omega=0.88")
 
 
-def batch_replicas(n: int = 256, sweeps: int = 10_000, seed: int = MASTER_SEED ^ 3) -> List[Job]:
+def batch_replicas(n: int = 256, sweeps: int = 10_000, seed: int = MASTER_SEED ^ 3,
+                   offgrid: bool = False) -> List[Job]:
     """Replica table: L = 64 * 16**U (log-uniform 64..1024), x ~ U[0.2,0.8], omega ~ U[0.2,1.4].
 
-    Every L is rounded to a multiple of 32 (whole 32-site words per row);
-    replicas with L_raw >= 256 are bit-packed, the rest stored as int8."""
+    Replicas with L_raw >= 256 are bit-packed with L rounded to a multiple of
+    32; the rest are stored as int8, with L rounded to a multiple of 32 as
+    well (whole 32-site words per row) or, with `offgrid`, to a multiple of 4
+    (the same draws, so the same replicas up to the rounding of the small ones)."""
     rng = np.random.default_rng(seed)
     jobs = []
     for i in range(n):
         raw = 64.0 * 16.0 ** rng.random()
-        L = int(round(raw / 32.0)) * 32
         layout = "bitpacked" if raw >= 256.0 else "int8"
+        step = 4 if (offgrid and layout == "int8") else 32
+        L = int(round(raw / step)) * step
         L = max(64, min(1024, L))
         x = float(rng.uniform(0.2, 0.8))
         w = float(rng.uniform(0.2, 1.4))

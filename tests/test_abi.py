@@ -138,3 +138,41 @@ def test_header_compiles_as_c99(tmp_path):
                    "}\n")
     subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"), "-c",
                     str(src), "-o", str(tmp_path / "use_kk.o")], check=True)
+
+
+def _job_bytes(L, layout, keep):
+    lib = kk.load()
+    r = kk.Replica(L, layout, 0.5, 0.5, 1, 10, 0)
+    out = ctypes.c_uint64()
+    st = lib.kk_server_job_bytes(ctypes.byref(r), keep, ctypes.byref(out))
+    assert st == kk.KK_OK, lib.kk_last_error()
+    return out.value
+
+
+@pytest.mark.parametrize("L", [128, 256, 1024, 2048, 32768])
+def test_server_job_charge_bounds_every_phase(L):
+    # The server admits a job by its charge, so the charge must cover the most
+    # a job's handle holds at once: its two lattice buffers plus either the
+    # placement keys (8 B per site) or, while it retires, the labelling arrays
+    # (8 B per site) and, when a bit-packed lattice is copied out, the
+    # one-byte-per-site unpack buffer beside them.
+    N = L * L
+    bits = _job_bytes(L, kk.LAYOUT_BITPACKED, 0)
+    bits_keep = _job_bytes(L, kk.LAYOUT_BITPACKED, 1)
+    assert bits >= 2 * (N // 8) + 8 * N
+    assert bits_keep >= 2 * (N // 8) + 8 * N + N
+    assert 0 < bits_keep - bits <= N
+    i8 = _job_bytes(L, kk.LAYOUT_INT8, 0)
+    assert i8 == _job_bytes(L, kk.LAYOUT_INT8, 1) >= 2 * N + 8 * N
+    assert _job_bytes(L, kk.LAYOUT_AUTO, 1) == bits_keep   # L % 32 == 0: auto is bit-packed
+    # small tables only on top
+    assert bits_keep < 2 * (N // 8) + 9 * N + 4 * (N // 4096 + 1) + (1 << 20)
+
+
+def test_server_job_charge_rejects_invalid_jobs():
+    lib = kk.load()
+    out = ctypes.c_uint64()
+    for L, layout in ((0, 0), (6, 1), (100, 2), (64, 5), (32772, 1)):
+        r = kk.Replica(L, layout, 0.5, 0.5, 1, 10, 0)
+        assert lib.kk_server_job_bytes(ctypes.byref(r), 0, ctypes.byref(out)) == kk.KK_EINVAL
+    assert lib.kk_server_job_bytes(None, 0, ctypes.byref(out)) == kk.KK_EINVAL

@@ -78,8 +78,7 @@ def test_server_mix_equals_alone(chunk):
 
 def test_server_small_budget_queues_fifo():
     jobs = mix()
-    fp = [2 * (j.L * j.L // (8 if j.layout == "bitpacked" else 1)) + 8 * j.L * j.L + 4 * (j.L * j.L // 4096 + 1)
-          + (64 << 10) for j in jobs]
+    fp = [kk.server_job_bytes(j, keep_lattice=True) for j in jobs]
     budget = max(fp) + min(fp)   # the largest job fits, but rarely with much beside it
     say(f"case server budget {budget} bytes")
     srv = kk.Server(hbm_budget_bytes=budget, chunk_sweeps=20, keep_lattice=True)

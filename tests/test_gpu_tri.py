@@ -179,6 +179,22 @@ def test_tri_autotune_restores_state_and_keeps_results(L, H, scheme):
         kk.Sim(64, 0.5, 0.7, 1).tri_autotune(2)
 
 
+@pytest.mark.parametrize("L,H,scheme", [(1028, 1028, "classes"), (1027, 1029, "mpkk")])
+def test_tri_autotune_never_loses_to_the_default_tile(L, H, scheme):
+    # the default tile (here a grid-cut rectangle) is one of the timed candidates,
+    # so the tuned tile is never measurably slower than it
+    print(f"case tri autotune vs default {L}x{H} {scheme}", flush=True)
+    s = kk.Sim(L, 0.5, 0.88, 5, geometry="triangular", rows=H, scheme=scheme)
+    default = s.tri_get_tile()
+    assert default[0] != default[1] or default[0] not in (320, 256, 192, 160, 128, 96, 64, 48, 32, 16)
+    s.sweep(5)
+    ms_def, n_def = s.sweep_timed(60)
+    cols, rows, us = s.tri_autotune(20)
+    ms_tuned, n_tuned = s.sweep_timed(60)
+    assert ms_tuned <= 1.25 * ms_def, ((cols, rows, ms_tuned), (default, ms_def))
+    s.close()
+
+
 def test_runner_series_and_resume(tmp_path):
     import io
     import json
