@@ -90,3 +90,17 @@ def test_400_grid_batched_matches_oracle_goldens():
         assert s.stats()[0] == 100_000
         _check_final(rec, s, s.stats()[2])
     b.close()
+def test_4096_full_run_matches_oracle_goldens():
+    rec = _load(OUT_4096)
+    job = wl.big_4096()
+    assert (rec["L"], rec["composition"], rec["omega"], rec["seed"], rec["sweeps"]) == \
+        (job.L, job.composition, job.omega, job.seed, job.sweeps)
+    say(f"case {job.tag}: {job.sweeps} sweeps, lattice hash every 1000")
+    sim = kk.Sim(job.L, job.composition, job.omega, job.seed, layout="bitpacked")
+    for k, want in enumerate(rec["cadence"]):
+        sim.sweep(1000)
+        assert sim.stats()[0] == want["t"]
+        assert sim.energy()[0] == want["n_unlike"], (want["t"],)
+        assert oracle.lattice_hash(sim.get_lattice()) == want["lattice_hash"], (want["t"],)
+    _check_final(rec, sim, sim.stats()[2])
+    sim.close()
