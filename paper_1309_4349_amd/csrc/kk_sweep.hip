@@ -451,11 +451,14 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void sweep_kernel(SweepParams
 
 
 // Per-row random state for one sweep: the two direction planes and, for each
-// of the three rejectable classes of moves, (u10 < T_hi) and (u10 == T_hi)
-// over the row's 32 sites.  8 words replace the 12 random planes once the
-// comparisons are done.
+// of the three rejectable classes of moves (slot j), the plane of sites whose
+// 42-bit uniform U = u10 * 2^32 + ext32 lies below the slot's threshold T_j.
+// The 10-bit prefix decides every site whose u10 differs from T_j's top bits;
+// for the others (about 3 sites in 1024 per slot) the low word ext32 is drawn
+// here, once per sweep, so the phases decide with bitwise logic alone and
+// never branch on a tie.
 struct RowRand {
-  uint32_t d0, d1, lt0, lt1, lt2, eq0, eq1, eq2;
+  uint32_t d0, d1, acc0, acc1, acc2;
 };
 
 // The threshold prefixes pass through an empty asm so that their per-bit masks
@@ -466,22 +469,46 @@ __device__ __forceinline__ uint32_t opaque_sgpr(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& p, RowRand& q) {
+// pl: the 12 random planes of 32 sites of true row ytrue from true column
+// xtrue (xtrue + b may pass the wrap only for L % 32 != 0 or L < 32).
+__device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& p, int ytrue, int xtrue, uint64_t t,
+                                         RowRand& q) {
   q.d0 = pl[0];
   q.d1 = pl[1];
-  if (p.acc.hi[0] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[0]), q.lt0, q.eq0); else { q.lt0 = 0xFFFFFFFFu; q.eq0 = 0u; }
-  if (p.acc.hi[1] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[1]), q.lt1, q.eq1); else { q.lt1 = 0xFFFFFFFFu; q.eq1 = 0u; }
-  if (p.acc.hi[2] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[2]), q.lt2, q.eq2); else { q.lt2 = 0xFFFFFFFFu; q.eq2 = 0u; }
+  uint32_t lt[3], eq[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (p.acc.hi[j] < 1024u) cmp10(pl, opaque_sgpr(p.acc.hi[j]), lt[j], eq[j]);
+    else {
+      lt[j] = 0xFFFFFFFFu;
+      eq[j] = 0u;
+    }
+  }
+  uint32_t tie = eq[0] | eq[1] | eq[2];
+  while (tie) {  // u10 equals a threshold prefix: the low 32 bits of U decide
+    const int bp = __builtin_ctz(tie);
+    tie &= tie - 1u;
+    int x = xtrue + bp;
+    if (x >= p.L) x = imod(x, p.L);
+    const Philox4 e = philox10((uint32_t)ytrue, (uint32_t)x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
+    const uint32_t xs = (uint32_t)x & 3u;
+    const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (((eq[j] >> bp) & 1u) && ext < p.acc.lo[j]) lt[j] |= 1u << bp;
+  }
+  q.acc0 = lt[0];
+  q.acc1 = lt[1];
+  q.acc2 = lt[2];
 }
 
 
 // Decide the exchanges of the centres in `cmask` of one 32-site word.
 // v: the word (0), its west/east neighbours (1, 2), the same three in the
 // row above (3..5) and below (6..8), and the words two rows above / below
-// (9, 10).  (ytrue, xtrue) are the true coordinates of bit 0 (xtrue + b may
-// pass the wrap only for L % 32 != 0 or L < 32).  Returns the accepted centres.
+// (9, 10).  Returns the accepted centres.
 __device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand& q, const SweepParams& p,
-                                                uint32_t cmask, int ytrue, int xtrue, uint64_t t) {
+                                                uint32_t cmask) {
   const uint32_t c0 = v[0], n0 = v[3], s0 = v[6];
   const uint32_t cE = __builtin_amdgcn_alignbit(v[2], c0, 1);
   const uint32_t cW = __builtin_amdgcn_alignbit(c0, v[1], 31);
@@ -511,24 +538,11 @@ __device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand
   const uint32_t m2 = bop3<kMaj3>(M1, M2, M3) ^ c0;
   uint32_t F = A;
   if (p.acc.restricted) {
-    // rejectable: m in {1,2,3} for omega > 0 (dU = 6,4,2), {5,6,7} for omega < 0
+    // rejectable: m in {1,2,3} for omega > 0 (dU = 6,4,2), {5,6,7} for omega < 0;
+    // slot j = (m & 3) - 1 holds the acceptance plane of that move class
     const uint32_t rm = bop3<KK_TT(~KK_TA & (KK_TB | KK_TC))>(m2 ^ p.acc.negmask, m0, m1);
-    const uint32_t ltsel = bsel(m1, bsel(m0, q.lt2, q.lt1), q.lt0);
-    const uint32_t eqsel = bsel(m1, bsel(m0, q.eq2, q.eq1), q.eq0);
-    F = bop3<KK_TT(KK_TA & (~KK_TB | KK_TC))>(A, rm, ltsel);
-    uint32_t tie = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(A, rm, eqsel);
-    while (tie) {  // u10 equals the threshold prefix: the low 32 bits decide
-      const int bp = __builtin_ctz(tie);
-      tie &= tie - 1u;
-      int x = xtrue + bp;
-      if (x >= p.L) x = imod(x, p.L);
-      const Philox4 e = philox10((uint32_t)ytrue, (uint32_t)x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
-      const uint32_t xs = (uint32_t)x & 3u;
-      const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
-      const uint32_t j = ((((m1 >> bp) & 1u) << 1) | ((m0 >> bp) & 1u)) - 1u;
-      const uint32_t lo = j == 0 ? p.acc.lo[0] : j == 1 ? p.acc.lo[1] : p.acc.lo[2];
-      if (ext < lo) F |= 1u << bp;
-    }
+    const uint32_t accsel = bsel(m1, bsel(m0, q.acc2, q.acc1), q.acc0);
+    F = bop3<KK_TT(KK_TA & (~KK_TB | KK_TC))>(A, rm, accsel);
   }
   return F;
 }
@@ -570,7 +584,7 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
   for (int k = 0; k < KU; ++k) {
     // class mask: the unit's base pattern rotated left by a (its period is 4)
     const uint32_t cmask = __builtin_amdgcn_alignbit(okm[k * 2 + H], okm[k * 2 + H], (32 - a) & 31);
-    F[k] = decide_word(v[k], rr[k][H], p, cmask, yrow[k * 2 + H], xw[k], t);
+    F[k] = decide_word(v[k], rr[k][H], p, cmask);
   }
   unsigned count = 0;
 #pragma unroll
@@ -694,9 +708,9 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
       if (ok) {
         uint32_t pl[kPlanes];
         gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
-        row_rand(pl, p, rr[k][h]);
+        row_rand(pl, p, ytab[r0 + h], xtab[w], t, rr[k][h]);
       } else {
-        rr[k][h] = RowRand{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        rr[k][h] = RowRand{0u, 0u, 0u, 0u, 0u};
       }
     }
   }
@@ -820,7 +834,7 @@ __device__ __forceinline__ unsigned cyc_phase(uint32_t* S, const SweepParams& p,
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
     const uint32_t cmask = __builtin_amdgcn_alignbit(okm[k * 2 + H], okm[k * 2 + H], (32 - a) & 31);
-    F[k] = decide_word(v[k], rr[k][H], p, cmask, yrow[k * 2 + H], xw[k], t);
+    F[k] = decide_word(v[k], rr[k][H], p, cmask);
   }
   unsigned count = 0;
 #pragma unroll
@@ -902,7 +916,7 @@ __device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p
       for (int h = 0; h < 2; ++h) {
         uint32_t pl[kPlanes];
         gen_planes_at(p, yrow[2 * k + h], xw[k], xw[k], t, pl);
-        row_rand(pl, p, rr[k][h]);
+        row_rand(pl, p, yrow[2 * k + h], xw[k], t, rr[k][h]);
       }
     }
     // one wave computes the sweep's class order; every wave has read the
