@@ -97,7 +97,9 @@ __device__ void store_word(const SweepParams& p, int y, int x0, uint32_t v, int 
         for (int k = 0; k < 8; ++k) d[k] = spread4((v >> (4 * k)) & 0xFu);
       }
     } else {
-      for (int b = 0; b < nbits; ++b) row[x0 + b] = (uint8_t)((v >> b) & 1u);
+      // a ragged last word: nbits is a multiple of 4 (x0 and L are)
+      uint32_t* d = reinterpret_cast<uint32_t*>(row + x0);
+      for (int k = 0; k < nbits / 4; ++k) d[k] = spread4((v >> (4 * k)) & 0xFu);
     }
   }
 }
@@ -164,11 +166,16 @@ __device__ __forceinline__ uint32_t load_word_at(const SweepParams& p, int y, in
     }
     return v;
   }
+  // the word passes the end of the row: eight 4-byte pieces, each inside the
+  // row (x0 and L are multiples of 4), the start of each wrapped; the loads
+  // are independent, so they are all in flight at once
   uint32_t v = 0;
   int x = x0;
-  for (int b = 0; b < 32; ++b) {
-    v |= (uint32_t)(row[x] & 1u) << b;
-    x = (x + 1 == L) ? 0 : x + 1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v |= pack4(*reinterpret_cast<const uint32_t*>(row + x)) << (4 * k);
+    x += 4;
+    if (x >= L) x -= L;
   }
   return v;
 }
