@@ -40,20 +40,58 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks and unit counts
 HBM_PEAK_GBS = 8000.0
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
-VALU_PEAK_GOPS = CUS * LANES * CLOCK_HZ / 1e9   # int32 lane-ops/s, one VALU op per lane per clock
+# VALU peak: 256 CUs x 4 SIMDs x 16 lanes per clock = one fp32 FMA per lane per
+# clock (the published 157.3 TFLOP/s counts an FMA as two flops and uses the
+# packed two-wide form).  It is the roofline's unit: every algorithmic
+# instruction is priced at its measured issue cost relative to an fp32 FMA.
+VALU_PEAK_GOPS = CUS * LANES * CLOCK_HZ / 1e9   # fp32-FMA-equivalent lane-ops/s
 
-# Algorithmic cost of one attempt of the bit-sliced sweep, in 32-bit VALU lane-ops
-# (one lane-op = one 32-bit integer/bitwise operation on one lane):
-#   random planes: 3 Philox4x32-10 blocks per 32-site word per sweep, 10 rounds x
-#     (2 v_mad_u64_u32 + 2 three-input xors) = 40 per block -> 120 / 32      = 3.75
-#   threshold planes: 3 bit-sliced 10-bit compares (less-than and equal) per
-#     32-site word per sweep, 2 ops per bit -> 60 / 32                       = 1.875
-#   decision of the 8 centres of a word in one phase: 8 funnel shifts, 12
-#     partner/neighbour selects, 1 activity mask, 5 + 6 counter ops, 2 + 6 + 2
-#     threshold selection, 1 class-mask rotate = 43; applying the accepted
-#     swaps (4 direction splits, 3 + 3 shifts/xors) and counting them (2) = 13
-#     -> 56 / 8                                                              = 7.0
-OPS_PER_ATTEMPT = 3.75 + 1.875 + 7.0
+# Algorithmic instruction mix of one attempt, in 32-bit VALU lane-ops by kind
+# (one lane-op = one instruction on one lane).  "fast" is the bitwise/add
+# class (v_xor, v_and, v_or, v_bitop3, v_add, v_xnor), which gfx950 issues in
+# about 0.6 of the cycles of an FMA; v_mad_u64_u32, v_alignbit, v_mul and
+# v_bcnt issue at the FMA rate (kk_valu_issue_cycles measures both on the box).
+# Square torus, bit-sliced sweep:
+#   random planes: 3 Philox4x32-10 blocks per 32-site word per sweep, 10 rounds
+#     x (2 v_mad_u64_u32 + 2 three-input xors)         -> 60 mad + 60 fast / 32
+#   acceptance planes: 3 bit-sliced 10-bit compares per word per sweep, 25 ops
+#     each (a borrow op and an XNOR per bit, a 5-op AND tree)   -> 75 fast / 32
+#   decision of the 8 centres of a word in one phase: 9 funnel shifts (8
+#     neighbour alignments, the class mask), 28 selects/counter/threshold ops;
+#     applying the accepted exchanges: 4 direction splits, 2 shifts, 1 xor3, 2
+#     edge tests; counting: 1 and, 1 popcount, 1 add          -> per word-phase
+#     9 alignbit + 37 fast + 2 shift + 1 bcnt, over 8 attempts
+SQUARE_MIX = {"mad_u64_u32": 60 / 32, "alignbit": 9 / 8, "lshl": 2 / 8, "bcnt": 1 / 8,
+              "fast": (60 + 75) / 32 + 37 / 8}
+OPS_PER_ATTEMPT = sum(SQUARE_MIX.values())
+
+
+def valu_weights(cycles):
+    """Issue cost of each instruction kind relative to an fp32 FMA, from the
+    measured cycles per wave64 instruction (None: every kind at the FMA rate)."""
+    if not cycles:
+        return {k: 1.0 for k in ("mad_u64_u32", "alignbit", "lshl", "bcnt", "mul_lo", "fast")}
+    f = cycles["fma_f32"]
+    fast = (cycles["xor"] + cycles["bitop3"] + cycles["add"]) / 3.0
+    return {"mad_u64_u32": cycles["mad_u64_u32"] / f, "alignbit": cycles["alignbit"] / f,
+            "lshl": cycles["lshl"] / f, "bcnt": cycles["bcnt"] / f, "mul_lo": cycles["mul_lo"] / f,
+            "fast": fast / f}
+
+
+def weighted_ops(mix, weights):
+    return sum(n * weights[k] for k, n in mix.items())
+
+
+def roofline_alu(mix, weights, attempts_per_s):
+    """The roofline entry of a VALU-bound kernel at the given attempt rate."""
+    w = weighted_ops(mix, weights)
+    ops = w * attempts_per_s / 1e9
+    return {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
+            "unit": "TOP/s (fp32-FMA-equivalent VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
+            "ops_per_attempt": round(sum(mix.values()), 3), "weighted_ops_per_attempt": round(w, 3),
+            "instruction_mix": {k: round(v, 4) for k, v in mix.items()}}
+
+
 # HBM-side bytes per launch of the sweep kernel on this workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes recorded in
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
@@ -188,16 +226,16 @@ def small_64(cpu: bool):
     return out
 
 
-# Algorithmic cost of one attempt on the triangular lattice, in 32-bit VALU
-# lane-ops: one Philox4x32-10 block per two sites (20: a block's words 0-1
-# serve the even site of a pair and words 2-3 the odd one, so a kernel that
-# computes a whole block per centre does twice the method's random-number
-# work), the partner direction and uniform (3), 12 neighbour addresses (2
-# each, 24), 12 unlike tests and their sum (24), the threshold lookup and
-# compare (3), the swap (2) -> 76.  Algorithmic bytes: each site read and
-# written once per sweep (2 B).  The whole-sweep tile kernel recomputes a halo
-# on top of this.
-TRI_OPS_PER_ATTEMPT = 76.0
+# Algorithmic mix of one attempt on the triangular lattice: one Philox4x32-10
+# block per two sites (10 mad + 10 fast: a block's words 0-1 serve the even
+# site of a pair and words 2-3 the odd one, so a kernel that computes a whole
+# block per centre does twice the method's random-number work), the partner
+# direction (one multiply-high) and uniform (2 fast), 12 neighbour addresses
+# (24), 12 unlike tests and their sum (24), the threshold lookup and compare
+# (3), the swap (2) -> 76.  Algorithmic bytes: each site read and written once
+# per sweep (2 B).  The whole-sweep tile kernel recomputes a halo on top of this.
+TRI_MIX = {"mad_u64_u32": 10.0, "mul_lo": 1.0, "fast": 65.0}
+TRI_OPS_PER_ATTEMPT = sum(TRI_MIX.values())
 
 
 def tri_batch(n: int, L: int, sweeps: int, n_plain: int):
@@ -248,7 +286,7 @@ def tri_batch(n: int, L: int, sweeps: int, n_plain: int):
             "speedup": rate / plain, "layout": info}
 
 
-def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 1000):
+def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 1000, weights=None):
     """Attempts/s of the triangular helical lattice (the paper's geometry)."""
     import torch
 
@@ -269,7 +307,6 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 
     ms, launches = sim.sweep_timed(profile_sweeps)
     per_launch_s = ms / 1e3 / launches
     per_launch = N * profile_sweeps / launches
-    ops = TRI_OPS_PER_ATTEMPT * per_launch / per_launch_s / 1e9
     hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
     nab, _ = sim.energy()
     sim.close()
@@ -279,11 +316,9 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 
         traffic = TRI_PROFILED_TRAFFIC["bytes_per_launch"]
     out = {"workload": f"triangular helical {L}x{L} int8, x={x}, omega={w}, {sweeps} sweeps",
            "value": rate, "unit": "attempts/s", "n_unlike_over_3N": nab / (3 * N),
-           "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
-                        "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
+           "roofline": {**roofline_alu(TRI_MIX, weights, per_launch / per_launch_s),
                         "traffic": traffic, "kernel": "tri_tile_sweep" if sim_tile[0] else "tri_phase",
-                        "kernel_us": round(per_launch_s * 1e6, 3),
-                        "launches": int(launches), "ops_per_attempt": TRI_OPS_PER_ATTEMPT,
+                        "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
                         "tile": {"cols": sim_tile[0], "rows": sim_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
     log(f"[bench] triangular {L}^2: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
@@ -304,14 +339,15 @@ def triangular(sweeps: int, profile_sweeps: int, cpu: bool, batch_sweeps: int = 
     return out
 
 
-# One literal-MPKK attempt: one Philox block per two domains (20), k draw
-# amortised (0), direction and uniform (3), 12 neighbour indices (24), 12
-# unlike tests and their sum (24), threshold (3), writing the domain's result
-# (13) -> 87.
-MPKK_OPS_PER_ATTEMPT = 87.0
+# One literal-MPKK attempt: one Philox block per two domains (10 mad + 10
+# fast), k draw amortised (0), direction (one multiply-high) and uniform (2),
+# 12 neighbour indices (24), 12 unlike tests and their sum (24), threshold (3),
+# writing the domain's result (13) -> 87.
+MPKK_MIX = {"mad_u64_u32": 10.0, "mul_lo": 1.0, "fast": 76.0}
+MPKK_OPS_PER_ATTEMPT = sum(MPKK_MIX.values())
 
 
-def mpkk(steps: int, bias_steps: int, cpu: bool):
+def mpkk(steps: int, bias_steps: int, cpu: bool, weights=None):
     """Throughput of the literal MPKK and its bias against the exact chain."""
     import math
 
@@ -335,7 +371,6 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
     ms, launches = sim.sweep_timed(50)
     per_launch_s = ms / 1e3 / launches
     per_launch = N * 50 / launches
-    ops = MPKK_OPS_PER_ATTEMPT * per_launch / per_launch_s / 1e9
     hbm = BYTES_PER_ATTEMPT_INT8 * per_launch / per_launch_s / 1e9
     sim.close()
     traffic = None
@@ -344,11 +379,9 @@ def mpkk(steps: int, bias_steps: int, cpu: bool):
         traffic = MPKK_PROFILED_TRAFFIC["bytes_per_launch"]
     out = {"workload": f"literal MPKK, triangular helical {L}x{H} int8, x={x}, omega={w}, {steps} steps",
            "value": rate, "unit": "attempts/s",
-           "roofline": {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
-                        "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(ops / VALU_PEAK_GOPS, 4),
+           "roofline": {**roofline_alu(MPKK_MIX, weights, per_launch / per_launch_s),
                         "traffic": traffic, "kernel": "mpkk_tile_step" if mp_tile[0] else "mpkk_iter",
-                        "kernel_us": round(per_launch_s * 1e6, 3),
-                        "launches": int(launches), "ops_per_attempt": MPKK_OPS_PER_ATTEMPT,
+                        "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
                         "tile": {"cols": mp_tile[0], "rows": mp_tile[1]},
                         "hbm_achieved_GBps": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 5)}}
     log(f"[bench] mpkk {L}x{H}: {rate:.3e} attempts/s, {per_launch_s * 1e6:.2f} us/launch")
@@ -445,10 +478,11 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int, offgrid: bool = False):
             "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
 
 
-def grid_400(rounds: int, every: int):
+def grid_400(rounds: int, every: int, weights=None):
     """The 12-run 400x400 grid (3 compositions x 4 omegas, int8) advanced together
     in one batch, with every run's species-1 cluster histogram taken every
-    `every` sweeps, against the same runs advanced one after another."""
+    `every` sweeps, against the same runs advanced one after another; and the
+    rooflines of the plain single-lattice sweep kernel and of the batch."""
     import torch
 
     from paper_1309_4349_amd import kk
@@ -458,6 +492,7 @@ def grid_400(rounds: int, every: int):
     sites = sum(j.L * j.L for j in jobs)
     b = kk.Batch(jobs)
     tw, th, _ = b.autotune(5)
+    plan = b.info()
     b.run()
     for i in range(len(jobs)):
         b.sim(i).cluster_hist(1)
@@ -469,6 +504,12 @@ def grid_400(rounds: int, every: int):
             b.sim(i).cluster_hist(1)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    # the sweeps alone (no histograms), for the batch's roofline
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    tsw = time.perf_counter() - t0
     b.close()
     rate = sites * every * rounds / tb
     sims = [kk.Sim(j.L, j.composition, j.omega, j.seed, layout=j.layout) for j in jobs]
@@ -481,14 +522,33 @@ def grid_400(rounds: int, every: int):
         s.cluster_hist(1)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    # the plain path's sweep kernel on one 400^2 lattice, timed on the library's stream
+    ms, launches = sims[5].sweep_timed(500)
+    per_launch_s = ms / 1e3 / launches
+    ptile = sims[5].get_tile()
     for s in sims:
         s.close()
     plain = sites * every / tp
-    log(f"[bench] 400^2 grid: batched {rate:.3e} attempts/s (tiles <= {tw}x{th}), one after another {plain:.3e}")
+    n1 = jobs[0].L * jobs[0].L
+    plain_roof = {**roofline_alu(SQUARE_MIX, weights, n1 / per_launch_s),
+                  "kernel": f"halo_kernel<int8, {ptile[0]}, {ptile[2]}>", "kernel_us": round(per_launch_s * 1e6, 3),
+                  "launches": int(launches), "tile": {"words": ptile[0], "rows": ptile[1], "units_per_thread": ptile[2]},
+                  "algorithmic_bytes_per_launch": int(BYTES_PER_ATTEMPT_INT8 * n1),
+                  "hbm_achieved_GBps": round(BYTES_PER_ATTEMPT_INT8 * n1 / per_launch_s / 1e9, 1),
+                  "hbm_frac": round(BYTES_PER_ATTEMPT_INT8 * n1 / per_launch_s / 1e9 / HBM_PEAK_GBS, 5)}
+    batch_sweep_rate = sites * every / tsw
+    batch_roof = {**roofline_alu(SQUARE_MIX, weights, batch_sweep_rate),
+                  "kernel": "batch_tile_kernel (whole batch run of the 12 lattices, launch gaps included)",
+                  "us_per_sweep": round(tsw / every * 1e6, 3), "plan": plan}
+    log(f"[bench] 400^2 grid: batched {rate:.3e} attempts/s (tiles <= {tw}x{th}; sweeps alone "
+        f"{batch_sweep_rate:.3e}, {tsw / every * 1e6:.1f} us per sweep of all 12), one after another {plain:.3e}; "
+        f"plain sweep kernel {per_launch_s * 1e6:.2f} us per 400^2 sweep")
     return {"workload": "12 runs of 400x400 int8, x in {0.3,0.5,0.7} x omega in {0.3,0.6,0.9,1.2}, "
                         f"histogram of every run every {every} sweeps",
             "batched_attempts_per_s": rate, "rounds": rounds, "sweeps_per_round": every,
-            "tile_words": tw, "tile_rows": th, "sequential_attempts_per_s": plain, "speedup": rate / plain}
+            "tile_words": tw, "tile_rows": th, "sequential_attempts_per_s": plain, "speedup": rate / plain,
+            "batched_sweeps_only_attempts_per_s": batch_sweep_rate, "roofline_batched": batch_roof,
+            "roofline_plain_single": plain_roof}
 
 
 def serving(n_saturated: int, n_light: int, light_rate: float, chunk: int):
@@ -566,6 +626,15 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4}))
         return
 
+    # issue cost of each instruction kind on this device (prices the rooflines)
+    try:
+        cycles = kk.valu_issue_cycles()
+    except kk.KKError as e:
+        log(f"[bench] VALU probe failed ({e}): every instruction priced at the FMA rate")
+        cycles = None
+    weights = valu_weights(cycles)
+    log(f"[bench] VALU issue cycles per wave64 instruction: {cycles}")
+
     job = wl.big_4096(args.sweeps)
     N = job.L * job.L
     log(f"[bench] creating {job.tag}")
@@ -595,25 +664,24 @@ def main():
     ms, launches = sim.sweep_timed(args.profile_sweeps)
     per_launch_s = ms / 1e3 / launches
     attempts_per_launch = N * args.profile_sweeps / launches
-    ops = OPS_PER_ATTEMPT * attempts_per_launch / per_launch_s / 1e9
     hbm = BYTES_PER_ATTEMPT_BITS * attempts_per_launch / per_launch_s / 1e9
     tw, th, ku = sim.get_tile()
     traffic = None
     if (kernel_sources_sha() == PROFILED_TRAFFIC["sources_sha256_prefix"]
             and (tw, th, ku) == PROFILED_TRAFFIC["tile"] and job.L == 4096):
         traffic = PROFILED_TRAFFIC["bytes_per_launch"]
-    roofline = {"bound": "alu", "achieved": round(ops / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 3),
-                "unit": "TOP/s (32-bit VALU lane-ops)",
-                "frac": round(ops / VALU_PEAK_GOPS, 4), "traffic": traffic,
+    roofline = {**roofline_alu(SQUARE_MIX, weights, attempts_per_launch / per_launch_s), "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes_per_launch": int(BYTES_PER_ATTEMPT_BITS * attempts_per_launch),
                 "kernel": f"halo_kernel<bitpacked, {tw}, {ku}>",
                 "kernel_us": round(per_launch_s * 1e6, 3), "launches": int(launches),
-                "ops_per_attempt": OPS_PER_ATTEMPT,
                 "hbm_achieved_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
                 "hbm_frac": round(hbm / HBM_PEAK_GBS, 5),
-                "tile": {"words": tw, "rows": th, "units_per_thread": ku}}
-    log(f"[bench] sweep kernel {per_launch_s * 1e6:.2f} us/launch, {ops:.0f} Gop/s, {hbm:.1f} GB/s algorithmic")
+                "tile": {"words": tw, "rows": th, "units_per_thread": ku},
+                "valu_issue_cycles": {k: round(v, 3) for k, v in (cycles or {}).items()},
+                "weights_rel_fma": {k: round(v, 3) for k, v in weights.items()}}
+    log(f"[bench] sweep kernel {per_launch_s * 1e6:.2f} us/launch, frac {roofline['frac']}, "
+        f"{hbm:.1f} GB/s algorithmic")
     # observables of the final state (labelling, N_AB and the random-neighbour draw)
     sim.sweep(1)
     torch.cuda.synchronize()
@@ -630,7 +698,7 @@ def main():
 
     grid = None
     if not args.no_batch:
-        grid = grid_400(args.grid_rounds, 1000)
+        grid = grid_400(args.grid_rounds, 1000, weights)
 
     served = None
     if not args.no_serve:
@@ -638,11 +706,11 @@ def main():
 
     tri = None
     if not args.no_tri:
-        tri = triangular(args.tri_sweeps, 100, not args.no_cpu, args.tri_batch_sweeps)
+        tri = triangular(args.tri_sweeps, 100, not args.no_cpu, args.tri_batch_sweeps, weights)
 
     mp = None
     if not args.no_mpkk:
-        mp = mpkk(args.mpkk_steps, args.mpkk_bias_steps, not args.no_cpu)
+        mp = mpkk(args.mpkk_steps, args.mpkk_bias_steps, not args.no_cpu, weights)
 
     small = small_64(not args.no_cpu)
 

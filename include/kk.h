@@ -514,6 +514,20 @@ void kk_server_destroy(kk_server *s);
 kk_status kk_sweep_noalloc(void *lattice, uint32_t L, uint32_t layout, double omega_kT, uint64_t seed, uint64_t t0,
                            uint64_t n_sweeps, unsigned long long *accepted, void *hip_stream);
 
+/* Measurement aid for pricing the kernels' VALU roofline: the SIMD cycles one
+ * wave64 instruction of each kind below occupies on the current device, from
+ * timed probe kernels (eight independent chains per lane, 32 waves per CU),
+ * the device's CU count (4 SIMDs each) and its reported clock.  out[i] for
+ * i = KK_VALU_XOR, _BITOP3, _ALIGNBIT, _ADD, _MAD_U64_U32, _MUL_LO, _FMA_F32,
+ * _LSHL, _BCNT.
+ * Allocates a small buffer and blocks; KK_EDEVICE on a failed launch. */
+enum {
+    KK_VALU_XOR = 0, KK_VALU_BITOP3 = 1, KK_VALU_ALIGNBIT = 2, KK_VALU_ADD = 3,
+    KK_VALU_MAD_U64_U32 = 4, KK_VALU_MUL_LO = 5, KK_VALU_FMA_F32 = 6, KK_VALU_LSHL = 7, KK_VALU_BCNT = 8,
+    KK_VALU_PROBES = 9
+};
+kk_status kk_valu_issue_cycles(double out[KK_VALU_PROBES]);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *kk_last_error(void);
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkk.so")
 SOURCES = ["kk_sweep.hip", "kk_aux.hip", "kk_tri.hip", "kk_api.cpp", "kk_batch.cpp", "kk_tri_batch.cpp", "kk_serve.cpp",
-           "kk_noalloc.hip"]
+           "kk_noalloc.hip", "kk_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

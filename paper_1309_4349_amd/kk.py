@@ -34,7 +34,7 @@ EXPORTS = [
     "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
-    "kk_server_destroy", "kk_server_job_bytes", "kk_sweep_noalloc",
+    "kk_server_destroy", "kk_server_job_bytes", "kk_sweep_noalloc", "kk_valu_issue_cycles",
 ]
 
 
@@ -163,6 +163,7 @@ def load(path: str = LIB_PATH):
         "kk_server_get_stats": [P, ctypes.POINTER(ServerStats)],
         "kk_sweep_noalloc": [P, U32, U32, D, U64, U64, U64, P, P],
         "kk_server_job_bytes": [ctypes.POINTER(Replica), U32, u64p],
+        "kk_valu_issue_cycles": [dp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -466,6 +467,16 @@ class TriBatch:
 def _replica(j) -> Replica:
     return Replica(j.L, _LAYOUTS[getattr(j, "layout", "auto")], float(j.composition), float(j.omega),
                    j.seed & (2**64 - 1), int(j.sweeps), _STARTS[getattr(j, "start", "random")])
+
+
+VALU_PROBES = ("xor", "bitop3", "alignbit", "add", "mad_u64_u32", "mul_lo", "fma_f32", "lshl", "bcnt")
+
+
+def valu_issue_cycles() -> dict:
+    """kk_valu_issue_cycles: SIMD cycles per wave64 instruction of each probed kind."""
+    out = (ctypes.c_double * len(VALU_PROBES))()
+    _check(load().kk_valu_issue_cycles(out))
+    return {k: out[i] for i, k in enumerate(VALU_PROBES)}
 
 
 def server_job_bytes(job, keep_lattice: bool = False) -> int:
