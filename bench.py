@@ -491,7 +491,7 @@ def grid_400(rounds: int, every: int, weights=None):
     jobs = wl.grid_400(sweeps=every)
     sites = sum(j.L * j.L for j in jobs)
     b = kk.Batch(jobs)
-    tw, th, _ = b.autotune(5)
+    tw, th, _ = b.autotune(20)
     plan = b.info()
     b.run()
     for i in range(len(jobs)):

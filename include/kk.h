@@ -333,9 +333,10 @@ kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
 /* Autotune the tiles of the tiled replicas: time whole batch runs of
  * trial_sweeps sweeps (0 = 10) for tiles (words x at most rows) of
- * 8 x 128, 16 x 84, 8 x 64, 16 x 42, 8 x 32 and 8 x 16 (smaller tiles give more
- * workgroups when the batch holds little work, larger ones less halo work),
- * keep the fastest and re-plan.
+ * 8 x 128, 16 x 84, 8 x 64, 16 x 42, 8 x 32 and 8 x 16 at two units per
+ * thread, and 16 x 28, 16 x 20, 8 x 72, 8 x 50 and 8 x 32 at one unit per
+ * thread (smaller tiles give more workgroups when the batch holds little
+ * work, larger ones less halo work), keep the fastest and re-plan.
  * Every replica's lattice, sweep counter and counters are restored exactly
  * after the trials.  Outputs (any may be NULL): the chosen maximum tile width
  * (words) and height (rows) and the best trial's milliseconds per sweep.

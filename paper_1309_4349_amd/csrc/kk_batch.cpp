@@ -47,6 +47,7 @@ struct kk_batch {
   bool own_sims = true;
   int tile_th = kBatchTh;        // largest tile height of tiled replicas (rows, even)
   int tile_tww = kBatchMaxTww / 2;  // largest tile width of tiled replicas (words)
+  int tile_ku = 2;                  // units per thread of the tile kernel (1 or 2)
   // streams and events, created once
   hipStream_t sA = nullptr, sB = nullptr;  // large resident launch; uploads and joins
   hipStream_t sC = nullptr;                 // small resident launch
@@ -154,7 +155,7 @@ kk_status make_streams(kk_batch* b, void* hip_stream) {
 
 // Geometry of a replica's batch launch (resident: whole lattice; tiled: tiles
 // of max_tww (8 or 16) words by at most max_th rows).
-void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, SweepParams* p) {
+void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, int ku, SweepParams* p) {
   TileConfig tc;
   if (resident) {
     tc.cyclic = true;
@@ -167,12 +168,12 @@ void batch_geometry(const kk_sim* h, bool resident, int max_tww, int max_th, Swe
     tc.cyclic = false;
     tc.tww = max_tww;
     tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
-    while (!batch_tile_fits(tc.tww, tc.th)) {  // more rows of tiles until one fits a workgroup
+    while (!batch_tile_fits(tc.tww, tc.th, ku)) {  // more rows of tiles until one fits a workgroup
       ++ty;
       tc.th = std::min(h->L, (((h->L + ty - 1) / ty) + 1) & ~1);
     }
   }
-  tc.ku = 2;
+  tc.ku = resident ? 2 : ku;
   tile_geometry(h->L, tc, p);
   p->k0 = h->k0;
   p->k1 = h->k1;
@@ -192,7 +193,7 @@ kk_status batch_plan(kk_batch* b) {
     kk_sim* h = b->sims[i];
     const bool res = is_resident(h);
     SweepParams p{};
-    batch_geometry(h, res, b->tile_tww, b->tile_th, &p);
+    batch_geometry(h, res, b->tile_tww, b->tile_th, b->tile_ku, &p);
     const size_t tiles = res ? 1 : (size_t)p.tiles_x * (size_t)((h->L + p.th - 1) / p.th);
     b->count_off.push_back(b->ncounts);
     b->count_n.push_back(tiles);
@@ -272,14 +273,21 @@ kk_status batch_plan(kk_batch* b) {
   e = hipEventRecord(b->ev_fork, origin);
   for (hipStream_t bs : branches)
     if (e == hipSuccess) e = hipStreamWaitEvent(bs, b->ev_fork, 0);
-  for (int g = 0; g < ngroups && e == hipSuccess; ++g)
+  for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
     for (int r = 0; r < kBatchChunk && e == hipSuccess; ++r)
-      e = launch_batch_tiles(b->d_params, b->d_jobs + b->tg_off[g], b->tg_n[g], b->d_ctl + 2 * g, b->tg_stream[g]);
-  if (e == hipSuccess && n_small)
+      e = launch_batch_tiles(b->d_params, b->d_jobs + b->tg_off[g], b->tg_n[g], b->d_ctl + 2 * g, (unsigned)r,
+                             b->tile_ku, b->tg_stream[g]);
+    if (e == hipSuccess) e = launch_batch_advance(b->d_ctl + 2 * g, (unsigned)kBatchChunk, b->tg_stream[g]);
+  }
+  if (e == hipSuccess && n_small) {
     e = launch_batch_resident(b->d_params, b->d_res, (int)n_small, b->small_lds, true, b->d_ctl + 2 * kCtlSmall, b->sC);
-  if (e == hipSuccess && n_large)
+    if (e == hipSuccess) e = launch_batch_advance(b->d_ctl + 2 * kCtlSmall, (unsigned)kBatchChunk, b->sC);
+  }
+  if (e == hipSuccess && n_large) {
     e = launch_batch_resident(b->d_params, b->d_res + n_small, (int)n_large, b->res_lds, false,
                               b->d_ctl + 2 * kCtlLarge, b->sA);
+    if (e == hipSuccess) e = launch_batch_advance(b->d_ctl + 2 * kCtlLarge, (unsigned)kBatchChunk, b->sA);
+  }
   for (size_t i = 0; i < branches.size() && e == hipSuccess; ++i) {
     e = hipEventRecord(b->tg_done[i % kMaxTileGroups], branches[i]);
     if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->tg_done[i % kMaxTileGroups], 0);
@@ -383,7 +391,7 @@ kk_status kk_batch_run(kk_batch* b) {
     if (b->sweeps[i] > 0x7FFFFFFFull) return set_error(KK_EINVAL, "at most 2^31-1 sweeps per replica per run");
     const bool res = is_resident(h);
     SweepParams& p = params[i];
-    batch_geometry(h, res, b->tile_tww, b->tile_th, &p);
+    batch_geometry(h, res, b->tile_tww, b->tile_th, b->tile_ku, &p);
     p.t0 = h->t;
     p.accepted = b->d_counts + b->count_off[i];
     // resident replicas sweep in place; tiled ones ping-pong src -> dst -> src ...
@@ -477,15 +485,20 @@ kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_w
     return KK_OK;
   };
   const std::vector<uint64_t> sweeps0 = b->sweeps;
-  const int th0 = b->tile_th, tw0 = b->tile_tww;
-  int best_th = th0, best_tw = tw0;
+  const int th0 = b->tile_th, tw0 = b->tile_tww, ku0 = b->tile_ku;
+  int best_th = th0, best_tw = tw0, best_ku = ku0;
   double best_ms = 1e300;
   kk_status st = KK_OK;
-  static const int cand[][2] = {{8, 128}, {16, 84}, {8, 64}, {16, 42}, {8, 32}, {8, 16}};
+  // (words, rows, units per thread): large tiles for batches that fill the
+  // device, small one-unit-per-thread tiles that spread a few mid-sized
+  // replicas over many workgroups
+  static const int cand[][3] = {{8, 128, 2}, {16, 84, 2}, {8, 64, 2}, {16, 42, 2}, {8, 32, 2}, {8, 16, 2},
+                                {16, 28, 1}, {16, 20, 1}, {8, 72, 1}, {8, 50, 1}, {8, 32, 1}};
   for (const auto& c : cand) {
     const int tw = c[0], th = c[1];
     b->tile_th = th;
     b->tile_tww = tw;
+    b->tile_ku = c[2];
     st = batch_replan(b, b->sims, std::vector<uint64_t>(n, trial_sweeps));
     if (st == KK_OK) st = kk_batch_run(b);  // warm-up (also checks the plan)
     double ms = 0.0;
@@ -501,11 +514,13 @@ kk_status kk_batch_autotune(kk_batch* b, uint32_t trial_sweeps, uint32_t* tile_w
       best_ms = ms;
       best_th = th;
       best_tw = tw;
+      best_ku = c[2];
     }
   }
   free_saved();
   b->tile_th = st == KK_OK ? best_th : th0;
   b->tile_tww = st == KK_OK ? best_tw : tw0;
+  b->tile_ku = st == KK_OK ? best_ku : ku0;
   const kk_status ps = batch_replan(b, b->sims, sweeps0);
   if (st == KK_OK) st = ps;
   if (st != KK_OK) return st;

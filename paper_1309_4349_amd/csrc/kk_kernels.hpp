@@ -31,31 +31,34 @@ struct SweepParams {
 hipError_t launch_sweep(const SweepParams& p, int layout, bool cyclic, int ku, int threads, hipStream_t stream);
 
 // Batch kernels.  Tiled replicas: one workgroup per (replica, tile) job and one
-// launch per sweep; the sweep index lives in ctl[0] and the last workgroup to
-// finish advances it (ctl[1] counts finished workgroups), so a captured
-// graph of launches can be replayed.  A replica runs p.nsweeps sweeps from
+// launch per sweep; ctl[0] holds the run sweep at which the current chunk of a
+// captured graph starts, each tile launch adds its position `rel` in the chunk,
+// and launch_batch_advance (one thread, the last node of a branch) moves ctl[0]
+// on by the chunk, so the graph replays unchanged.  A replica runs p.nsweeps sweeps from
 // p.t0, ping-ponging between p.src (its lattice at the start) and p.dst.  Resident replicas (L % 32 == 0,
 // 2 <= L/32 <= kResidentMaxC): one launch, one workgroup per replica running
 // all of its sweeps with the whole lattice in LDS.
 constexpr int kBatchMaxTww = 16, kBatchTh = 128, kBatchThreads = 768;
-// Tiled replicas run in 512-thread workgroups (two per CU), two units per
-// thread, in tiles 8 or 16 words wide: a tile of tww words by th rows fits
-// when its (th + 28) / 2 computed row pairs times tww + 2 words stay within
-// 1024 units.
+// Tiled replicas run in 512-thread workgroups, ku (1 or 2) units per thread,
+// in tiles 8 or 16 words wide: a tile of tww words by th rows fits when its
+// (th + 28) / 2 computed row pairs times tww + 2 words stay within ku * 512
+// units.
 constexpr int kBatchTileThreads = 512;
-constexpr bool batch_tile_fits(int tww, int th) {
-  return (tww == 8 || tww == 16) && th >= 2 && th <= kBatchTh && ((th + 28) / 2) * (tww + 2) <= 2 * kBatchTileThreads;
+constexpr bool batch_tile_fits(int tww, int th, int ku = 2) {
+  return (tww == 8 || tww == 16) && (ku == 1 || ku == 2) && th >= 2 && th <= kBatchTh &&
+         ((th + 28) / 2) * (tww + 2) <= ku * kBatchTileThreads;
 }
 struct BatchTileJob {
   int rep, tile;
 };
-hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
-                              hipStream_t stream);
+hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, const unsigned* ctl,
+                              unsigned rel, int ku, hipStream_t stream);
+hipError_t launch_batch_advance(unsigned* ctl, unsigned step, hipStream_t stream);
 // small: the 256-thread kernel for replicas of at most kResidentSmallMaxC words
 // per row.  A launch runs up to kBatchChunk sweeps from sweep ctl[0] of the run
-// and advances ctl[0] by kBatchChunk (see launch_batch_tiles).
+// (launch_batch_advance then moves ctl[0] on by kBatchChunk).
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
-                                 unsigned* ctl, hipStream_t stream);
+                                 const unsigned* ctl, hipStream_t stream);
 // Sweeps per replay of a batch graph: kBatchChunk tile launches per tile group
 // and one resident launch of kBatchChunk sweeps.
 constexpr int kBatchChunk = 64;

@@ -779,7 +779,9 @@ __device__ __forceinline__ void add_block_count(uint32_t* red_lds, unsigned coun
   if (threadIdx.x == 0) {
     unsigned long long tot = 0;
     for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red_lds[wv];
-    *dst += tot;
+    // one workgroup per address: an add without a returned value does not wait
+    // for a read of the old sum at the end of the kernel
+    atomicAdd(dst, tot);
   }
 }
 
@@ -961,27 +963,25 @@ __global__ __launch_bounds__(KU == 1 ? 1024 : 768) void cyc_kernel(SweepParams p
 // ---------------------------------------------------------------------------
 // Batch kernels
 // ---------------------------------------------------------------------------
-// Sweep hand-off of the batch kernels, which a captured graph replays: a
-// launch starts at sweep ctl[0] of the run and the last workgroup to finish
-// advances it by `step` for the next launch (ctl[1] counts finished
-// workgroups).  Device-scope atomics order the hand-off; lattice writes reach
-// the next launch through the kernel boundary, so no fence is needed.
-__device__ __forceinline__ void batch_advance(unsigned* ctl, unsigned s, unsigned step) {
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&ctl[1], 1u);
-    if (prev == gridDim.x - 1) {
-      __hip_atomic_store(&ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl[0], s + step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
+// Sweep hand-off of the batch kernels, which a captured graph replays: ctl[0]
+// holds the run sweep at which the current chunk of the graph starts; a tile
+// launch adds its own position in the chunk (a kernel argument), a resident
+// launch runs the whole chunk, and a one-thread kernel at the end of each
+// branch advances ctl[0] by the chunk for the next replay.  Stream order and
+// the kernel boundaries order every step, so no workgroup touches a shared
+// counter.
+__global__ void batch_advance_kernel(unsigned* ctl, unsigned step) { ctl[0] += step; }
 
+// KU = 2: tiles of up to 1024 units; KU = 1: up to 512 units, twice the
+// waves per unit, which hides more latency when small tiles spread a batch
+// over many workgroups.
+template <int KU>
 __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
-                                                                   unsigned* ctl) {
+                                                                   const unsigned* ctl, unsigned rel) {
   extern __shared__ uint32_t S[];
   // the sweep index and the job are independent loads; the replica's
   // parameters (sweep count and both buffers included) follow the job
-  const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + rel;
   const BatchTileJob job = jobs[blockIdx.x];
   SweepParams p = reps[job.rep];
   if (s < (unsigned)p.nsweeps) {
@@ -996,15 +996,14 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
     // tile column may be ragged
     unsigned count;
     if (p.layout == kLayoutBits) {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, 2>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutBits, 16, 2>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, KU>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutBits, 16, KU>(S, p, job.tile);
     } else {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, 2>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutInt8, 16, 2>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, KU>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutInt8, 16, KU>(S, p, job.tile);
     }
     add_block_count(S + p.R * HaloGeom<16>::ST, count, p.accepted + job.tile);
   }
-  batch_advance(ctl, s, 1u);
 }
 
 // All resident replicas in one launch, one workgroup each: the width is a
@@ -1013,7 +1012,7 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
 // staging and the final store.  The reduction area sits past the largest
 // resident lattice (rows L+4, stride <= 36).
 __global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const SweepParams* reps, const int* ids,
-                                                                           unsigned* ctl) {
+                                                                           const unsigned* ctl) {
   extern __shared__ uint32_t S[];
   const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   SweepParams p = reps[ids[blockIdx.x]];
@@ -1034,14 +1033,13 @@ __global__ __launch_bounds__(kBatchThreads) void batch_resident_all_kernel(const
     }
     add_block_count(S + (p.R + 4) * 36, count, p.accepted);
   }
-  batch_advance(ctl, s, (unsigned)kBatchChunk);
 }
 
 // Small resident replicas (L <= 32 * kResidentSmallMaxC: at most 512 units)
 // in 256-thread workgroups, three per CU.
 __global__ __launch_bounds__(kResidentSmallThreads, 3) void batch_resident_small_kernel(const SweepParams* reps,
                                                                                        const int* ids,
-                                                                                       unsigned* ctl) {
+                                                                                       const unsigned* ctl) {
   extern __shared__ uint32_t S[];
   const unsigned s = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   SweepParams p = reps[ids[blockIdx.x]];
@@ -1058,7 +1056,6 @@ __global__ __launch_bounds__(kResidentSmallThreads, 3) void batch_resident_small
     }
     add_block_count(S + (p.R + 4) * 36, count, p.accepted);
   }
-  batch_advance(ctl, s, (unsigned)kBatchChunk);
 }
 
 }  // namespace
@@ -1135,15 +1132,24 @@ size_t batch_tile_lds_bytes() {
 
 size_t batch_resident_lds_bytes(int L) { return ((size_t)(L + 4) * 36 + 17) * sizeof(uint32_t); }
 
-hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, unsigned* ctl,
-                              hipStream_t stream) {
-  hipLaunchKernelGGL(batch_tile_kernel, dim3(njobs), dim3(kBatchTileThreads), batch_tile_lds_bytes(), stream, reps, jobs,
-                     ctl);
+hipError_t launch_batch_tiles(const SweepParams* reps, const BatchTileJob* jobs, int njobs, const unsigned* ctl,
+                              unsigned rel, int ku, hipStream_t stream) {
+  if (ku == 1)
+    hipLaunchKernelGGL(batch_tile_kernel<1>, dim3(njobs), dim3(kBatchTileThreads), batch_tile_lds_bytes(), stream,
+                       reps, jobs, ctl, rel);
+  else
+    hipLaunchKernelGGL(batch_tile_kernel<2>, dim3(njobs), dim3(kBatchTileThreads), batch_tile_lds_bytes(), stream,
+                       reps, jobs, ctl, rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(unsigned* ctl, unsigned step, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(1), 0, stream, ctl, step);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_resident(const SweepParams* reps, const int* ids, int n, size_t lds_bytes, bool small,
-                                 unsigned* ctl, hipStream_t stream) {
+                                 const unsigned* ctl, hipStream_t stream) {
   if (small)
     hipLaunchKernelGGL(batch_resident_small_kernel, dim3(n), dim3(kResidentSmallThreads), lds_bytes, stream, reps,
                        ids, ctl);
