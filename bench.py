@@ -97,18 +97,24 @@ def roofline_alu(mix, weights, attempts_per_s):
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
-PROFILED_TRAFFIC = {"sources_sha256_prefix": "9c62b97bbe2863ae", "tile": (16, 128, 2),
-                    "bytes_per_launch": 4772573}
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3c57b42b495a0ff", "tile": (16, 128, 2),
+                    "bytes_per_launch": 4768477}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
-TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (256, 256),
-                        "bytes_per_launch": 35855573}
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "0a358e4a29639be4", "tile": (256, 256),
+                        "bytes_per_launch": 35855642}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 # And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
 # 257 x 256 tiles (profiles/mpkk_tile_step_4098x4095.md).
-MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a1e5780aa3169772", "tile": (257, 256),
-                         "bytes_per_launch": 35114392}
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "0a358e4a29639be4", "tile": (257, 256),
+                         "bytes_per_launch": 35114180}
+# The 400^2 int8 paths (profiles/halo_kernel_400_int8.md): the plain sweep
+# kernel with 2 x 16 tiles, and the batch tile kernel at the autotuner's 16 x 28
+# tiles, one unit per thread, over the 12 runs.
+GRID_PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3c57b42b495a0ff", "plain_tile": (2, 16, 1),
+                         "plain_bytes_per_launch": 879504, "batch_tile": (16, 28),
+                         "batch_bytes_per_launch": 6703798}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
@@ -530,7 +536,10 @@ def grid_400(rounds: int, every: int, weights=None):
         s.close()
     plain = sites * every / tp
     n1 = jobs[0].L * jobs[0].L
+    same_src = kernel_sources_sha() == GRID_PROFILED_TRAFFIC["sources_sha256_prefix"]
     plain_roof = {**roofline_alu(SQUARE_MIX, weights, n1 / per_launch_s),
+                  "traffic": GRID_PROFILED_TRAFFIC["plain_bytes_per_launch"]
+                  if same_src and tuple(ptile) == GRID_PROFILED_TRAFFIC["plain_tile"] else None,
                   "kernel": f"halo_kernel<int8, {ptile[0]}, {ptile[2]}>", "kernel_us": round(per_launch_s * 1e6, 3),
                   "launches": int(launches), "tile": {"words": ptile[0], "rows": ptile[1], "units_per_thread": ptile[2]},
                   "algorithmic_bytes_per_launch": int(BYTES_PER_ATTEMPT_INT8 * n1),
@@ -538,6 +547,9 @@ def grid_400(rounds: int, every: int, weights=None):
                   "hbm_frac": round(BYTES_PER_ATTEMPT_INT8 * n1 / per_launch_s / 1e9 / HBM_PEAK_GBS, 5)}
     batch_sweep_rate = sites * every / tsw
     batch_roof = {**roofline_alu(SQUARE_MIX, weights, batch_sweep_rate),
+                  "traffic": GRID_PROFILED_TRAFFIC["batch_bytes_per_launch"]
+                  if same_src and (tw, th) == GRID_PROFILED_TRAFFIC["batch_tile"] else None,
+                  "algorithmic_bytes_per_launch": int(BYTES_PER_ATTEMPT_INT8 * sites),
                   "kernel": "batch_tile_kernel (whole batch run of the 12 lattices, launch gaps included)",
                   "us_per_sweep": round(tsw / every * 1e6, 3), "plan": plan}
     log(f"[bench] 400^2 grid: batched {rate:.3e} attempts/s (tiles <= {tw}x{th}; sweeps alone "
@@ -596,6 +608,8 @@ def main():
     ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
     ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
     ap.add_argument("--mpkk-bias-steps", type=int, default=6000, help="measured steps per bias run (0 skips the bias runs)")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="only the 400^2 grid measurement (its JSON on one line), for profiling that path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -634,6 +648,10 @@ def main():
         cycles = None
     weights = valu_weights(cycles)
     log(f"[bench] VALU issue cycles per wave64 instruction: {cycles}")
+
+    if args.grid_only:
+        print(json.dumps({"grid_400": grid_400(args.grid_rounds, 1000, weights)}), flush=True)
+        return
 
     job = wl.big_4096(args.sweeps)
     N = job.L * job.L
