@@ -219,7 +219,8 @@ def small_64(cpu: bool):
     if cpu:
         import oracle
 
-        threads = oracle.set_threads(1)
+        threads = oracle.set_threads(0)  # the current count, restored below
+        oracle.set_threads(1)
         s = oracle.init(job.L, job.composition, job.seed)
         t0 = time.perf_counter()
         oracle.sweeps(s, job.omega, job.seed, 0, job.sweeps)

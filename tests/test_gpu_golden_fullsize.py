@@ -90,6 +90,8 @@ def test_400_grid_batched_matches_oracle_goldens():
         assert s.stats()[0] == 100_000
         _check_final(rec, s, s.stats()[2])
     b.close()
+
+
 def test_4096_full_run_matches_oracle_goldens():
     rec = _load(OUT_4096)
     job = wl.big_4096()
