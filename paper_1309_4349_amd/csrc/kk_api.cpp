@@ -36,8 +36,9 @@ void acceptance_table(double omega, uint64_t T[7], Accept* acc) {
     T[n] = (v < two42) ? (uint64_t)v : (uint64_t)1 << 42;
   }
   std::memset(acc, 0, sizeof *acc);
-  if (omega == 0.0) return;  // every unlike exchange is accepted
-  acc->restricted = 0xFFFFFFFFu;
+  // omega == 0: every unlike exchange is accepted, and every slot below holds
+  // 2^42 (prefix 1024), which accepts every site without a branch
+  acc->restricted = omega == 0.0 ? 0u : 0xFFFFFFFFu;
   acc->negmask = omega < 0.0 ? 0xFFFFFFFFu : 0u;
   // slot j covers m & 3 == j + 1 with m = n + 1: n = j (omega > 0) or n = 4 + j (omega < 0)
   for (int j = 0; j < 3; ++j) {

@@ -237,10 +237,11 @@ constexpr unsigned kMaj3 = KK_TT((KK_TA & KK_TB) | (KK_TA & KK_TC) | (KK_TB & KK
 // u - K from the least significant bit, lt' = maj(~u_k, K_k, lt), one
 // three-input op per bit; equality is the AND of u_k XNOR K_k, one XNOR per bit
 // and a tree of three-input ANDs.
-__device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& lt, uint32_t& eq) {
+__device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& lt, uint32_t& eq,
+                                      uint32_t bin = 0u, uint32_t em = 0xFFFFFFFFu) {
   constexpr unsigned kBorrow = KK_TT((~KK_TA & KK_TB) | (~KK_TA & KK_TC) | (KK_TB & KK_TC));
   constexpr unsigned kAnd3 = KK_TT(KK_TA & KK_TB & KK_TC);
-  uint32_t l = 0u, x[10];
+  uint32_t l = bin, x[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
     const uint32_t u = pl[11 - k];
@@ -249,7 +250,9 @@ __device__ __forceinline__ void cmp10(const uint32_t* pl, uint32_t K, uint32_t& 
     x[k] = ~(u ^ kb);
   }
   lt = l;
-  eq = bop3<kAnd3>(bop3<kAnd3>(x[0], x[1], x[2]), bop3<kAnd3>(x[3], x[4], x[5]), bop3<kAnd3>(x[6], x[7], x[8])) & x[9];
+  eq = bop3<kAnd3>(bop3<kAnd3>(bop3<kAnd3>(x[0], x[1], x[2]), bop3<kAnd3>(x[3], x[4], x[5]),
+                                bop3<kAnd3>(x[6], x[7], x[8])),
+                   x[9], em);
 }
 
 template <bool CYC>
@@ -476,6 +479,27 @@ __device__ __forceinline__ uint32_t opaque_sgpr(uint32_t v) {
   return v;
 }
 
+// Ties: u10 equals a threshold prefix, and the low 32 bits of U decide.  eq[j]
+// holds the tied sites of slot j among the 32 sites from true column xtrue of
+// true row ytrue (xtrue + b may pass the wrap only for L % 32 != 0 or L < 32);
+// the tied sites that lie below the threshold join lt[j].
+__device__ __forceinline__ void resolve_ties(const SweepParams& p, int ytrue, int xtrue, uint64_t t,
+                                             const uint32_t* eq, uint32_t* lt) {
+  uint32_t tie = eq[0] | eq[1] | eq[2];
+  while (tie) {
+    const int bp = __builtin_ctz(tie);
+    tie &= tie - 1u;
+    int x = xtrue + bp;
+    if (x >= p.L) x = imod(x, p.L);
+    const Philox4 e = philox10((uint32_t)ytrue, (uint32_t)x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
+    const uint32_t xs = (uint32_t)x & 3u;
+    const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (((eq[j] >> bp) & 1u) && ext < p.acc.lo[j]) lt[j] |= 1u << bp;
+  }
+}
+
 // pl: the 12 random planes of 32 sites of true row ytrue from true column
 // xtrue (xtrue + b may pass the wrap only for L % 32 != 0 or L < 32).
 __device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& p, int ytrue, int xtrue, uint64_t t,
@@ -491,22 +515,154 @@ __device__ __forceinline__ void row_rand(const uint32_t* pl, const SweepParams& 
       eq[j] = 0u;
     }
   }
-  uint32_t tie = eq[0] | eq[1] | eq[2];
-  while (tie) {  // u10 equals a threshold prefix: the low 32 bits of U decide
-    const int bp = __builtin_ctz(tie);
-    tie &= tie - 1u;
-    int x = xtrue + bp;
-    if (x >= p.L) x = imod(x, p.L);
-    const Philox4 e = philox10((uint32_t)ytrue, (uint32_t)x >> 2, (uint32_t)t, ctr_hi(t, kTagExt), p.k0, p.k1);
-    const uint32_t xs = (uint32_t)x & 3u;
-    const uint32_t ext = xs == 0 ? e.x : xs == 1 ? e.y : xs == 2 ? e.z : e.w;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (((eq[j] >> bp) & 1u) && ext < p.acc.lo[j]) lt[j] |= 1u << bp;
-  }
+  resolve_ties(p, ytrue, xtrue, t, eq, lt);
   q.acc0 = lt[0];
   q.acc1 = lt[1];
   q.acc2 = lt[2];
+}
+
+// N Philox4x32-10 blocks at once, round by round across the blocks: the
+// multiplies of different blocks are independent and issue back to back
+// instead of waiting on one block's chain.  c0..c3: counters in, outputs out.
+template <int N>
+__device__ __forceinline__ void philox10_n(uint32_t* c0, uint32_t* c1, uint32_t* c2, uint32_t* c3, uint32_t k0,
+                                           uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const uint64_t p0 = (uint64_t)c0[n] * 0xD2511F53u;
+      const uint64_t p1 = (uint64_t)c2[n] * 0xCD9E8D57u;
+      const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1[n], k0, 0x96);
+      const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3[n], k1, 0x96);
+      c1[n] = (uint32_t)p1;
+      c3[n] = (uint32_t)p0;
+      c0[n] = n0;
+      c2[n] = n2;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Ties of NR rows on the segment grid (no site index wraps): each pass takes
+// the next tied site of every row and draws the NR extension words together,
+// so the passes follow the largest per-row tie count in the wave (one or two)
+// rather than the sum over rows, and the NR Philox chains overlap.
+template <int NR>
+__device__ __forceinline__ void resolve_ties_grid(const SweepParams& p, const int* y, const int* x, uint64_t t,
+                                                  const uint32_t (*eq)[3], uint32_t (*lt)[3]) {
+  uint32_t tie[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) tie[i] = eq[i][0] | eq[i][1] | eq[i][2];
+  const uint32_t tl = (uint32_t)t, th = ctr_hi(t, kTagExt);
+  for (;;) {
+    uint32_t left = 0u;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) left |= tie[i];
+    if (!left) break;
+    uint32_t c0[NR], c1[NR], c2[NR], c3[NR], bit[NR], xs[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const uint32_t m = tie[i];
+      bit[i] = m & (0u - m);  // the next tied site (none: 0, and the draw below is unused)
+      tie[i] = m & (m - 1u);
+      const uint32_t xsite = (uint32_t)x[i] + (uint32_t)(31 - __clz((int)bit[i]));
+      xs[i] = xsite & 3u;
+      c0[i] = (uint32_t)y[i];
+      c1[i] = xsite >> 2;
+      c2[i] = tl;
+      c3[i] = th;
+    }
+    philox10_n<NR>(c0, c1, c2, c3, p.k0, p.k1);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      // word xs of the block, by bitwise selects (a branch here would split
+      // the NR chains again)
+      const uint32_t s1 = 0u - (xs[i] & 1u), s2 = 0u - (xs[i] >> 1);
+      const uint32_t ext = bsel(s2, bsel(s1, c3[i], c2[i]), bsel(s1, c1[i], c0[i]));
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (ext < p.acc.lo[j]) lt[i][j] |= eq[i][j] & bit[i];
+    }
+  }
+}
+
+// Random state of NR rows whose words sit on the 32-site segment grid
+// (x % 32 == 0 and x + 32 <= L): the 3 NR Philox blocks are drawn together,
+// then the 3 NR compares, then the rare ties.  A slot whose threshold prefix is 1024 or more accepts
+// every site: its compare runs with a borrow-in (u < 1023 + 1) and an empty
+// equality mask instead of a branch.
+template <int NR>
+__device__ __forceinline__ void rand_rows_grid(const SweepParams& p, uint64_t t, const int* y, const int* x,
+                                               RowRand* q) {
+  const uint32_t tl = (uint32_t)t, thi = ctr_hi(t, kTagSweep);
+  uint32_t c0[NR * 3], c1[NR * 3], c2[NR * 3], c3[NR * 3];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const uint32_t g4 = (uint32_t)(x[i] >> 5) * 4u;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      c0[3 * i + b] = (uint32_t)y[i];
+      c1[3 * i + b] = g4 + (uint32_t)b;
+      c2[3 * i + b] = tl;
+      c3[3 * i + b] = thi;
+    }
+  }
+  philox10_n<NR * 3>(c0, c1, c2, c3, p.k0, p.k1);
+  uint32_t pl[NR][kPlanes];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      pl[i][4 * b] = c0[3 * i + b];
+      pl[i][4 * b + 1] = c1[3 * i + b];
+      pl[i][4 * b + 2] = c2[3 * i + b];
+      pl[i][4 * b + 3] = c3[3 * i + b];
+    }
+  }
+  // The compares run bit by bit across the rows: each bit of a threshold
+  // prefix becomes one all-zeros / all-ones scalar mask (a signed one-bit
+  // field extract), shared by the rows' borrow chains (u < K) and equality
+  // chains (u == K), one three-input op per bit and chain.
+  constexpr unsigned kBorrow = KK_TT((~KK_TA & KK_TB) | (~KK_TA & KK_TC) | (KK_TB & KK_TC));
+  constexpr unsigned kEqStep = KK_TT(KK_TA & ~(KK_TB ^ KK_TC));
+  uint32_t lt[NR][3], eq[NR][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const uint32_t hi = p.acc.hi[j];
+    const bool all = hi >= 1024u;
+    const uint32_t K = opaque_sgpr(all ? 1023u : hi);
+    const uint32_t bin = all ? 0xFFFFFFFFu : 0u, em = all ? 0u : 0xFFFFFFFFu;
+    uint32_t l[NR], e[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      l[i] = bin;
+      e[i] = em;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      const uint32_t kb = (uint32_t)((int32_t)(K << (31 - k)) >> 31);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const uint32_t u = pl[i][11 - k];  // planes 2 .. 11: bits 9 .. 0 of u10
+        l[i] = bop3<kBorrow>(u, kb, l[i]);
+        e[i] = bop3<kEqStep>(e[i], u, kb);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      lt[i][j] = l[i];
+      eq[i][j] = e[i];
+    }
+  }
+  // one test for all rows, so that no Philox block sinks past a tie loop
+  uint32_t anytie = 0u;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) anytie |= eq[i][0] | eq[i][1] | eq[i][2];
+  if (anytie) resolve_ties_grid<NR>(p, y, x, t, eq, lt);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) q[i] = RowRand{pl[i][0], pl[i][1], lt[i][0], lt[i][1], lt[i][2]};
 }
 
 
@@ -543,15 +699,13 @@ __device__ __forceinline__ uint32_t decide_word(const uint32_t* v, const RowRand
   const uint32_t m0 = ~(bop3<kXor3>(X1, X2, o3) ^ c0);
   const uint32_t m1 = bop3<kXor3>(M1, M2, M3) ^ c0;
   const uint32_t m2 = bop3<kMaj3>(M1, M2, M3) ^ c0;
-  uint32_t F = A;
-  if (p.acc.restricted) {
-    // rejectable: m in {1,2,3} for omega > 0 (dU = 6,4,2), {5,6,7} for omega < 0;
-    // slot j = (m & 3) - 1 holds the acceptance plane of that move class
-    const uint32_t rm = bop3<KK_TT(~KK_TA & (KK_TB | KK_TC))>(m2 ^ p.acc.negmask, m0, m1);
-    const uint32_t accsel = bsel(m1, bsel(m0, q.acc2, q.acc1), q.acc0);
-    F = bop3<KK_TT(KK_TA & (~KK_TB | KK_TC))>(A, rm, accsel);
-  }
-  return F;
+  // rejectable: m in {1,2,3} for omega > 0 (dU = 6,4,2), {5,6,7} for omega < 0;
+  // slot j = (m & 3) - 1 holds the acceptance plane of that move class.  No
+  // branch on omega == 0: there every slot's plane is all ones.  (A branch
+  // here split the neighbourhood reads into two LDS round trips per unit.)
+  const uint32_t rm = bop3<KK_TT(~KK_TA & (KK_TB | KK_TC))>(m2 ^ p.acc.negmask, m0, m1);
+  const uint32_t accsel = bsel(m1, bsel(m0, q.acc2, q.acc1), q.acc0);
+  return bop3<KK_TT(KK_TA & (~KK_TB | KK_TC))>(A, rm, accsel);
 }
 
 template <int TWW>
@@ -603,15 +757,26 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
     const uint32_t Fpy = bop3<KK_TT(KK_TA & KK_TB & ~KK_TC)>(f, d1, d0);
     const uint32_t Fmy = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(f, d1, d0);
     const int b = base0[k] + H * ST;
-    // zero masks are harmless: the three common updates go out unconditionally
+    // zero masks are harmless: every update goes out unconditionally (the two
+    // carries into the neighbouring words are mostly zero, but a masked store
+    // costs more issue slots than an xor with zero)
     atomicXor(&S[b], f ^ (Fpx << 1) ^ (Fmx >> 1));
     atomicXor(&S[b + ST], Fpy);
     atomicXor(&S[b - ST], Fmy);
-    if (Fpx >> 31) atomicXor(&S[b + 1], 1u);
-    if (Fmx & 1u) atomicXor(&S[b - 1], 0x80000000u);
+    atomicXor(&S[b + 1], Fpx >> 31);
+    atomicXor(&S[b - 1], Fmx << 31);
     count += (unsigned)__builtin_popcount(f & imask[k][H]);
   }
   return count;
+}
+
+// Sum over a wavefront of a per-lane count below 256, from eight ballots
+// (scalar popcounts; no LDS round trip).
+__device__ __forceinline__ unsigned wave_sum8(unsigned c) {
+  unsigned s = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) s += (unsigned)__popcll(__ballot((c >> b) & 1u)) << b;
+  return s;
 }
 
 // Halo-tile sweep with a compile-time tile width: the LDS row stride is a
@@ -622,9 +787,12 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
 // conflict-free schedule makes that reordering exact), so the LDS latency of
 // the second unit hides behind the first.
 // One sweep of tile `tile` of the lattice described by p (halo mode).
-// Returns this thread's accepted count for the tile interior.
+// Returns the workgroup's accepted count for the tile interior (the same in
+// every thread).
 
-template <int LAYOUT, int TWW, int KU>
+// NRG: rows whose random state is drawn together on the segment grid (all 2 KU
+// of the thread's rows, or one unit's 2 where registers are tighter).
+template <int LAYOUT, int TWW, int KU, int NRG = 2 * KU>
 __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
   constexpr int C = HaloGeom<TWW>::C;
   constexpr int ST = HaloGeom<TWW>::ST;
@@ -649,6 +817,9 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     if (i < p.R) ytab[i] = imod(YT + i, p.L);
     else xtab[i - p.R] = imod(XL + 32 * (i - p.R), p.L);
   }
+  // the workgroup's accepted count, in the gap between the rows and the tables
+  uint32_t* acc_total = S + p.R * ST;
+  if (threadIdx.x == 0) *acc_total = 0u;
   __syncthreads();
 
   // global loads first; they complete while the random state is computed
@@ -668,6 +839,9 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
   uint32_t okm[KU * 2];                 // class-0 centre pattern of each row (0 for a unit beyond the tile)
   uint32_t imask[KU][2];
   RowRand rr[KU][2];
+  int ry[KU * 2], rx[KU * 2];  // true row and column of each of the thread's rows
+  bool okk[KU];
+  const bool grid = (p.L & 31) == 0;
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
     const int u = threadIdx.x + k * blockDim.x;
@@ -708,17 +882,50 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
       const int n = hi - lo;
       wm = (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) << (lo - Xw);
     }
+    okk[k] = ok;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int yv = YT + r0 + h;
       imask[k][h] = (ok && yv >= Y0 && yv < yend) ? wm : 0u;
-      if (ok) {
-        uint32_t pl[kPlanes];
-        gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
-        row_rand(pl, p, ytab[r0 + h], xtab[w], t, rr[k][h]);
-      } else {
-        rr[k][h] = RowRand{0u, 0u, 0u, 0u, 0u};
+      ry[2 * k + h] = ytab[r0 + h];
+      rx[2 * k + h] = xtab[w];
+      if (!grid) {
+        if (ok) {
+          uint32_t pl[kPlanes];
+          gen_planes_at(p, ytab[r0 + h], xtab[w], Xw, t, pl);
+          row_rand(pl, p, ytab[r0 + h], xtab[w], t, rr[k][h]);
+        } else {
+          rr[k][h] = RowRand{0u, 0u, 0u, 0u, 0u};
+        }
       }
+    }
+  }
+  if (grid) {
+    // all rows of the thread at once (a unit beyond the tile draws for a valid
+    // row and decides nothing: its centre masks are empty); a wave whose last
+    // units all lie beyond the tile skips them
+    RowRand rq[KU * 2];
+    if constexpr (KU == 1) {
+      rand_rows_grid<2>(p, t, ry, rx, rq);
+    } else if constexpr (NRG == KU * 2) {
+      if (__any(okk[KU - 1])) {
+        rand_rows_grid<KU * 2>(p, t, ry, rx, rq);
+      } else {
+        rand_rows_grid<KU * 2 - 2>(p, t, ry, rx, rq);
+        rq[KU * 2 - 2] = rq[KU * 2 - 1] = RowRand{0u, 0u, 0u, 0u, 0u};
+      }
+    } else {
+      static_assert(NRG == 2, "rows are drawn per thread or per unit");
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        if (k == 0 || __any(okk[k])) rand_rows_grid<2>(p, t, ry + 2 * k, rx + 2 * k, rq + 2 * k);
+        else rq[2 * k] = rq[2 * k + 1] = RowRand{0u, 0u, 0u, 0u, 0u};
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      rr[k][0] = rq[2 * k];
+      rr[k][1] = rq[2 * k + 1];
     }
   }
   // the class order is the same for the whole workgroup: the first wave
@@ -746,6 +953,10 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     // parity: a uniform branch keeps each row's random state in registers
     if (cls & 1u) count += halo_phase<ST, KU, 1>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
     else count += halo_phase<ST, KU, 0>(S, p, base0, yrow, xw, okm, rr, imask, a, t);
+    if (ph == 7) {  // each wave adds its count before the last barrier
+      const unsigned ws = wave_sum8(count);
+      if ((threadIdx.x & 63) == 0) atomicAdd(acc_total, ws);
+    }
     __syncthreads();
   }
 
@@ -766,7 +977,7 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     }
   }
 
-  return count;
+  return *acc_total;
 }
 
 // Block-wide sum of the per-thread accepted counts, added to *dst by thread 0.
@@ -786,10 +997,13 @@ __device__ __forceinline__ void add_block_count(uint32_t* red_lds, unsigned coun
 }
 
 template <int LAYOUT, int TWW, int KU>
-__global__ __launch_bounds__(KU == 1 ? 1024 : 768) void halo_kernel(SweepParams p) {
+__global__ __launch_bounds__(KU == 1 ? 1024 : 768)
+__attribute__((amdgpu_waves_per_eu(KU == 1 ? 4 : 3, KU == 1 ? 4 : 3))) void halo_kernel(SweepParams p) {
   extern __shared__ uint32_t S[];
-  const unsigned count = halo_tile_sweep<LAYOUT, TWW, KU>(S, p, xcd_tile((int)blockIdx.x, (int)gridDim.x));
-  add_block_count(S + p.R * HaloGeom<TWW>::ST, count, p.accepted + blockIdx.x);
+  const unsigned total = halo_tile_sweep<LAYOUT, TWW, KU>(S, p, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+  // one workgroup per address: an add without a returned value does not wait
+  // for a read of the old sum at the end of the kernel
+  if (threadIdx.x == 0) atomicAdd(p.accepted + blockIdx.x, (unsigned long long)total);
 }
 
 // ---------------------------------------------------------------------------
@@ -918,15 +1132,13 @@ __device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p
 #pragma unroll 1
   for (int s = 0; s < p.nsweeps; ++s) {
     const uint64_t t = p.t0 + (uint64_t)s;
+    // every word sits on the segment grid (L % 32 == 0); a unit beyond the
+    // lattice draws for row 0 and decides nothing
     RowRand rr[KU][2];
 #pragma unroll
-    for (int k = 0; k < KU; ++k) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint32_t pl[kPlanes];
-        gen_planes_at(p, yrow[2 * k + h], xw[k], xw[k], t, pl);
-        row_rand(pl, p, yrow[2 * k + h], xw[k], t, rr[k][h]);
-      }
+    for (int k = 0; k < KU; ++k) {  // per unit: these kernels keep more state in registers
+      const int rx[2] = {xw[k], xw[k]};
+      rand_rows_grid<2>(p, t, yrow + 2 * k, rx, rr[k]);
     }
     // one wave computes the sweep's class order; every wave has read the
     // previous one (right after the previous sweep's first barrier)
@@ -975,9 +1187,10 @@ __global__ void batch_advance_kernel(unsigned* ctl, unsigned step) { ctl[0] += s
 // KU = 2: tiles of up to 1024 units; KU = 1: up to 512 units, twice the
 // waves per unit, which hides more latency when small tiles spread a batch
 // over many workgroups.
+// Two workgroups per CU: four waves per SIMD, at most 128 VGPRs each.
 template <int KU>
-__global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs,
-                                                                   const unsigned* ctl, unsigned rel) {
+__global__ __launch_bounds__(kBatchTileThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs, const unsigned* ctl, unsigned rel) {
   extern __shared__ uint32_t S[];
   // the sweep index and the job are independent loads; the replica's
   // parameters (sweep count and both buffers included) follow the job
@@ -996,13 +1209,13 @@ __global__ __launch_bounds__(kBatchTileThreads) void batch_tile_kernel(const Swe
     // tile column may be ragged
     unsigned count;
     if (p.layout == kLayoutBits) {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, KU>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutBits, 16, KU>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, KU, 2>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutBits, 16, KU, 2>(S, p, job.tile);
     } else {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, KU>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutInt8, 16, KU>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, KU, 2>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutInt8, 16, KU, 2>(S, p, job.tile);
     }
-    add_block_count(S + p.R * HaloGeom<16>::ST, count, p.accepted + job.tile);
+    if (threadIdx.x == 0) atomicAdd(p.accepted + job.tile, (unsigned long long)count);
   }
 }
 
