@@ -790,9 +790,7 @@ __device__ __forceinline__ unsigned wave_sum8(unsigned c) {
 // Returns the workgroup's accepted count for the tile interior (the same in
 // every thread).
 
-// NRG: rows whose random state is drawn together on the segment grid (all 2 KU
-// of the thread's rows, or one unit's 2 where registers are tighter).
-template <int LAYOUT, int TWW, int KU, int NRG = 2 * KU>
+template <int LAYOUT, int TWW, int KU>
 __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepParams& p, int tile) {
   constexpr int C = HaloGeom<TWW>::C;
   constexpr int ST = HaloGeom<TWW>::ST;
@@ -901,25 +899,20 @@ __device__ __forceinline__ unsigned halo_tile_sweep(uint32_t* S, const SweepPara
     }
   }
   if (grid) {
-    // all rows of the thread at once (a unit beyond the tile draws for a valid
-    // row and decides nothing: its centre masks are empty); a wave whose last
-    // units all lie beyond the tile skips them
+    // row by row (a unit beyond the tile draws for a valid row and decides
+    // nothing: its centre masks are empty); a wave whose units of one index
+    // all lie beyond the tile skips them.  Drawing more rows at once, to
+    // overlap more Philox chains, measured slower: 16.3 us per 4096^2 sweep
+    // for a unit's two rows, 18.7 us for all four rows of a thread, against
+    // 16.2 us row by row.
     RowRand rq[KU * 2];
-    if constexpr (KU == 1) {
-      rand_rows_grid<2>(p, t, ry, rx, rq);
-    } else if constexpr (NRG == KU * 2) {
-      if (__any(okk[KU - 1])) {
-        rand_rows_grid<KU * 2>(p, t, ry, rx, rq);
-      } else {
-        rand_rows_grid<KU * 2 - 2>(p, t, ry, rx, rq);
-        rq[KU * 2 - 2] = rq[KU * 2 - 1] = RowRand{0u, 0u, 0u, 0u, 0u};
-      }
-    } else {
-      static_assert(NRG == 2, "rows are drawn per thread or per unit");
 #pragma unroll
-      for (int k = 0; k < KU; ++k) {
-        if (k == 0 || __any(okk[k])) rand_rows_grid<2>(p, t, ry + 2 * k, rx + 2 * k, rq + 2 * k);
-        else rq[2 * k] = rq[2 * k + 1] = RowRand{0u, 0u, 0u, 0u, 0u};
+    for (int k = 0; k < KU; ++k) {
+      if (k == 0 || __any(okk[k])) {
+        rand_rows_grid<1>(p, t, ry + 2 * k, rx + 2 * k, rq + 2 * k);
+        rand_rows_grid<1>(p, t, ry + 2 * k + 1, rx + 2 * k + 1, rq + 2 * k + 1);
+      } else {
+        rq[2 * k] = rq[2 * k + 1] = RowRand{0u, 0u, 0u, 0u, 0u};
       }
     }
 #pragma unroll
@@ -1136,10 +1129,9 @@ __device__ __forceinline__ unsigned cyc_sweeps(uint32_t* S, const SweepParams& p
     // lattice draws for row 0 and decides nothing
     RowRand rr[KU][2];
 #pragma unroll
-    for (int k = 0; k < KU; ++k) {  // per unit: these kernels keep more state in registers
-      const int rx[2] = {xw[k], xw[k]};
-      rand_rows_grid<2>(p, t, yrow + 2 * k, rx, rr[k]);
-    }
+    for (int k = 0; k < KU; ++k)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) rand_rows_grid<1>(p, t, yrow + 2 * k + h, xw + k, &rr[k][h]);
     // one wave computes the sweep's class order; every wave has read the
     // previous one (right after the previous sweep's first barrier)
     if (threadIdx.x < 64) {
@@ -1209,11 +1201,11 @@ void batch_tile_kernel(const SweepParams* reps, const BatchTileJob* jobs, const 
     // tile column may be ragged
     unsigned count;
     if (p.layout == kLayoutBits) {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, KU, 2>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutBits, 16, KU, 2>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutBits, 8, KU>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutBits, 16, KU>(S, p, job.tile);
     } else {
-      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, KU, 2>(S, p, job.tile);
-      else count = halo_tile_sweep<kLayoutInt8, 16, KU, 2>(S, p, job.tile);
+      if (p.tww == 8) count = halo_tile_sweep<kLayoutInt8, 8, KU>(S, p, job.tile);
+      else count = halo_tile_sweep<kLayoutInt8, 16, KU>(S, p, job.tile);
     }
     if (threadIdx.x == 0) atomicAdd(p.accepted + job.tile, (unsigned long long)count);
   }
