@@ -501,12 +501,14 @@ def grid_400(rounds: int, every: int, weights=None):
     tw, th, _ = b.autotune(20)
     plan = b.info()
     b.run()
+    b.cluster_hists(1)
     for i in range(len(jobs)):
         b.sim(i).cluster_hist(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(rounds):
         b.run()
+        b.cluster_hists(1)  # every run's labelling, one device wait
         for i in range(len(jobs)):
             b.sim(i).cluster_hist(1)
     torch.cuda.synchronize()

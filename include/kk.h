@@ -331,6 +331,16 @@ kk_status kk_batch_run(kk_batch *b);
  * kk_cluster_hist, kk_stats, ...).  The batch owns it: do not destroy it. */
 kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
+/* The cluster-size histogram of `species` (0 or 1) of every replica, the one
+ * kk_cluster_hist gives (Materials and Methods, "Cluster Analysis methods":
+ * the statistics taken regularly during a run), computed for all replicas
+ * with one wait on the device instead of one per replica.  The results are
+ * held by the replicas' handles: kk_cluster_hist on a borrowed handle then
+ * returns them without device work until the replica's lattice changes.
+ * KK_EINVAL for another species, KK_ESTATE for a poisoned batch or replica,
+ * KK_EDEVICE (batch poisoned) on a device error.  Blocking. */
+kk_status kk_batch_cluster_hists(kk_batch *b, int species);
+
 /* Autotune the tiles of the tiled replicas: time whole batch runs of
  * trial_sweeps sweeps (0 = 10) for tiles (words x at most rows) of
  * 8 x 128, 16 x 84, 8 x 64, 16 x 42, 8 x 32 and 8 x 16 at two units per

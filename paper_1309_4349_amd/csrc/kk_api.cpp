@@ -179,9 +179,8 @@ void free_all(kk_sim* h) {
   if (h->partials) (void)hipFree(h->partials);
   if (h->ccl.parent) (void)hipFree(h->ccl.parent);
   if (h->ccl.size) (void)hipFree(h->ccl.size);
-  if (h->ccl.hist) (void)hipFree(h->ccl.hist);
-  if (h->ccl.big) (void)hipFree(h->ccl.big);
-  if (h->ccl.big_count) (void)hipFree(h->ccl.big_count);
+  if (h->ccl.hist) (void)hipFree(h->ccl.hist);  // also holds big_count and big
+  if (h->hist_host) (void)hipHostFree(h->hist_host);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -857,48 +856,92 @@ kk_status kk_energy(kk_sim* h, uint64_t* n_unlike, double* energy_kT) {
   return KK_OK;
 }
 
+}  // extern "C"
+
+namespace kk {
+
+// Labelling buffers of a handle, made on its first histogram: parent and size
+// (N words each), then one block holding the small-size histogram, the count
+// of large sizes and their list, so that one copy brings back the histogram,
+// the count and the first kHistBigPrefix large sizes; its pinned host image.
+kk_status hist_buffers(kk_sim* h) {
+  if (h->ccl_ready) return KK_OK;
+  const size_t N = (size_t)h->L * h->H;
+  const unsigned big_cap = (unsigned)(N / kSmallSizes + 1);
+  kk_status st = dmalloc(h, (void**)&h->ccl.parent, N * 4);
+  if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.size, N * 4);
+  if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.hist, ((size_t)kSmallSizes + 1 + big_cap) * 4);
+  if (st == KK_OK && !h->hist_host) {
+    const hipError_t e = hipHostMalloc((void**)&h->hist_host, ((size_t)kSmallSizes + 1 + kHistBigPrefix) * 4,
+                                       hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      h->hist_host = nullptr;
+      st = set_error(KK_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+  }
+  if (st != KK_OK) return st;
+  h->ccl.big_count = h->ccl.hist + kSmallSizes;
+  h->ccl.big = h->ccl.hist + kSmallSizes + 1;
+  h->ccl.big_cap = big_cap;
+  h->ccl_ready = true;
+  return KK_OK;
+}
+
+bool hist_cached(const kk_sim* h, int species) { return h->hist_epoch == h->epoch && h->hist_species == species; }
+
+// Label species, count and histogram on `stream`, and copy the result block
+// to the pinned image.  The result is read by hist_finish once the stream has
+// drained.
+kk_status hist_enqueue(kk_sim* h, int species, hipStream_t stream) {
+  kk_status st = hist_buffers(h);
+  if (st != KK_OK) return st;
+  KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, h->H, species, h->ccl, h->geom != 0, stream));
+  const size_t words = (size_t)kSmallSizes + 1 + std::min<size_t>(h->ccl.big_cap, kHistBigPrefix);
+  KK_HIP(hipMemcpyAsync(h->hist_host, h->ccl.hist, words * 4, hipMemcpyDeviceToHost, stream));
+  return KK_OK;
+}
+
+// Turn the pinned image into the handle's cached histogram (sizes ascending).
+kk_status hist_finish(kk_sim* h, int species) {
+  const uint32_t* hs = h->hist_host;
+  const unsigned nbig = hs[kSmallSizes];
+  if (nbig > h->ccl.big_cap) return set_error(KK_EDEVICE, "cluster list overflow (%u > %u)", nbig, h->ccl.big_cap);
+  std::vector<uint32_t> big(hs + kSmallSizes + 1, hs + kSmallSizes + 1 + std::min<unsigned>(nbig, kHistBigPrefix));
+  if (nbig > kHistBigPrefix) {  // more large clusters than the copied prefix
+    big.resize(nbig);
+    KK_HIP(hipMemcpyAsync(big.data() + kHistBigPrefix, h->ccl.big + kHistBigPrefix, (nbig - kHistBigPrefix) * 4,
+                          hipMemcpyDeviceToHost, h->stream));
+    KK_HIP(hipStreamSynchronize(h->stream));
+  }
+  std::map<uint64_t, uint64_t> bigh;
+  for (uint32_t s : big) bigh[s] += 1;
+  h->hist_cache.clear();
+  for (int s = 1; s < kSmallSizes; ++s)
+    if (hs[s]) h->hist_cache.push_back(kk_hist_entry{(uint64_t)s, (uint64_t)hs[s]});
+  for (auto& kv : bigh) h->hist_cache.push_back(kk_hist_entry{kv.first, kv.second});
+  h->hist_epoch = h->epoch;
+  h->hist_species = species;
+  return KK_OK;
+}
+
+}  // namespace kk
+
+extern "C" {
+
 kk_status kk_cluster_hist(kk_sim* h, int species, kk_hist_entry* out, size_t cap, size_t* n_out) {
   KK_GUARD(h);
   if (species != 0 && species != 1) return set_error(KK_EINVAL, "species must be 0 or 1");
   if (!n_out) return set_error(KK_EINVAL, "n_out is NULL");
   if (cap > 0 && !out) return set_error(KK_EINVAL, "out is NULL with cap > 0");
-  const size_t N = (size_t)h->L * h->H;
-  if (!h->ccl_ready) {
-    kk_status st = dmalloc(h, (void**)&h->ccl.parent, N * 4);
-    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.size, N * 4);
-    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.hist, kSmallSizes * 4);
-    h->ccl.big_cap = (unsigned)(N / kSmallSizes + 1);
-    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.big, (size_t)h->ccl.big_cap * 4);
-    if (st == KK_OK) st = dmalloc(h, (void**)&h->ccl.big_count, 4);
+  if (!hist_cached(h, species)) {
+    // the result is cached until the lattice changes, so a size query
+    // followed by the fill labels only once
+    kk_status st = hist_enqueue(h, species, h->stream);
     if (st != KK_OK) return st;
-    h->ccl_ready = true;
-  }
-  if (h->hist_epoch != h->epoch || h->hist_species != species) {
-    // label, count and histogram on the device; the result is cached until the
-    // lattice changes, so a size query followed by the fill labels only once
-    KK_HIP(hipMemsetAsync(h->ccl.size, 0, N * 4, h->stream));
-    KK_HIP(hipMemsetAsync(h->ccl.hist, 0, kSmallSizes * 4, h->stream));
-    KK_HIP(hipMemsetAsync(h->ccl.big_count, 0, 4, h->stream));
-    KK_HIP(launch_ccl(h->lat[h->cur], h->layout, h->L, h->H, species, h->ccl, h->geom != 0, h->stream));
-    std::vector<unsigned> hs(kSmallSizes);
-    unsigned nbig = 0;
-    KK_HIP(hipMemcpyAsync(hs.data(), h->ccl.hist, kSmallSizes * 4, hipMemcpyDeviceToHost, h->stream));
-    KK_HIP(hipMemcpyAsync(&nbig, h->ccl.big_count, 4, hipMemcpyDeviceToHost, h->stream));
     KK_HIP(hipStreamSynchronize(h->stream));
-    if (nbig > h->ccl.big_cap) return set_error(KK_EDEVICE, "cluster list overflow (%u > %u)", nbig, h->ccl.big_cap);
-    std::vector<uint32_t> big(nbig);
-    if (nbig) {
-      KK_HIP(hipMemcpyAsync(big.data(), h->ccl.big, nbig * 4, hipMemcpyDeviceToHost, h->stream));
-      KK_HIP(hipStreamSynchronize(h->stream));
-    }
-    std::map<uint64_t, uint64_t> bigh;
-    for (uint32_t s : big) bigh[s] += 1;
-    h->hist_cache.clear();
-    for (int s = 1; s < kSmallSizes; ++s)
-      if (hs[s]) h->hist_cache.push_back(kk_hist_entry{(uint64_t)s, (uint64_t)hs[s]});
-    for (auto& kv : bigh) h->hist_cache.push_back(kk_hist_entry{kv.first, kv.second});
-    h->hist_epoch = h->epoch;
-    h->hist_species = species;
+    st = hist_finish(h, species);
+    if (st != KK_OK) return st;
   }
   const size_t n = h->hist_cache.size();
   *n_out = n;

@@ -190,13 +190,20 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
   }
 }
 
+// Also clears what the later passes accumulate into: the cluster sizes, the
+// small-size histogram and the count of large sizes.
 __global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species,
-                                                uint32_t* parent) {
+                                                uint32_t* parent, uint32_t* size, unsigned* hist,
+                                                unsigned* big_count) {
   const size_t n = (size_t)L * H;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, nth = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = tid; i < n; i += nth) {
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
     parent[i] = (site_bit(lat, layout, L, x, y) == species) ? (uint32_t)i : kNone;
+    size[i] = 0u;
   }
+  for (size_t i = tid; i < (size_t)kSmallSizes; i += nth) hist[i] = 0u;
+  if (tid == 0) *big_count = 0u;
 }
 
 __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, int L, int species,
@@ -373,7 +380,8 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, co
                       hipStream_t stream) {
   const size_t n = (size_t)L * H;
   const int g = grid_for(n, 256);
-  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, H, species, b.parent);
+  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, H, species, b.parent, b.size, b.hist,
+                     b.big_count);
   if (triangular) {
     hipLaunchKernelGGL(ccl_merge_tri, dim3(g), dim3(256), 0, stream, static_cast<const uint8_t*>(lat), L, H, species,
                        b.parent);
@@ -383,7 +391,9 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, co
   }
   hipLaunchKernelGGL(ccl_flatten, dim3(g), dim3(256), 0, stream, b.parent, L, H);
   hipLaunchKernelGGL(ccl_count, dim3(g), dim3(256), 0, stream, b.parent, L, H, b.size);
-  hipLaunchKernelGGL(ccl_hist, dim3(g < 1024 ? g : 1024), dim3(256), 0, stream, b.size, L, H, b.hist, b.big,
+  // each workgroup clears and flushes a whole LDS histogram, and every one of
+  // them adds into the hot small sizes: few workgroups, each streaming many sites
+  hipLaunchKernelGGL(ccl_hist, dim3(g < 128 ? g : 128), dim3(256), 0, stream, b.size, L, H, b.hist, b.big,
                      b.big_count, b.big_cap);
   return hipGetLastError();
 }

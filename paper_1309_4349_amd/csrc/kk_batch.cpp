@@ -537,6 +537,39 @@ kk_status kk_batch_sim(kk_batch* b, size_t i, kk_sim** sim_out) {
   return KK_OK;
 }
 
+kk_status kk_batch_cluster_hists(kk_batch* b, int species) {
+  if (!b) return set_error(KK_EINVAL, "NULL batch");
+  if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  if (species != 0 && species != 1) return set_error(KK_EINVAL, "species must be 0 or 1");
+  // every replica's own stream has finished its earlier work
+  for (kk_sim* h : b->sims) {
+    if (h->poisoned) return set_error(KK_ESTATE, "a replica is poisoned");
+    if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
+  }
+  // the labellings spread over the batch's streams (a small lattice's passes
+  // fill a fraction of the device), one wait per stream, then the read-back
+  hipStream_t streams[kMaxTileGroups + 3] = {b->sB, b->sA, b->sC};
+  int ns = 3;
+  for (int g = 0; g < kMaxTileGroups; ++g)
+    if (b->tg_stream[g]) streams[ns++] = b->tg_stream[g];
+  std::vector<kk_sim*> todo;
+  for (kk_sim* h : b->sims) {
+    if (hist_cached(h, species)) continue;
+    const kk_status st = hist_enqueue(h, species, streams[todo.size() % ns]);
+    if (st != KK_OK) {
+      b->poisoned = true;
+      return st;
+    }
+    todo.push_back(h);
+  }
+  for (int i = 0; i < ns; ++i) KB_HIP(hipStreamSynchronize(streams[i]));
+  for (kk_sim* h : todo) {
+    const kk_status st = hist_finish(h, species);
+    if (st != KK_OK) return st;
+  }
+  return KK_OK;
+}
+
 kk_status kk_batch_info(kk_batch* b, size_t* n_resident, size_t* n_tiled, size_t* n_tile_jobs) {
   if (!b) return set_error(KK_EINVAL, "NULL batch");
   if (n_resident) *n_resident = b->resident.size();

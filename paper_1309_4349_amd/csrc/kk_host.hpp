@@ -55,6 +55,7 @@ struct kk_sim {
   kk::TileConfig tile{};
   kk::CclBuffers ccl{};
   bool ccl_ready = false;
+  uint32_t* hist_host = nullptr;  // pinned image of the histogram block (hist_enqueue)
   int geom = 0;                          // 0 square torus; triangular helical int8 ring: 1 with the
                                          // conflict-free 16 classes, 2 with the literal MPKK cover
   kk::TriAccept tacc{};                  // triangular thresholds
@@ -70,6 +71,12 @@ struct kk_sim {
 namespace kk {
 // helpers shared with the batch engine (kk_api.cpp)
 kk_status device_alloc(void** p, size_t bytes);
+// cluster histograms: a handle's labelling is enqueued on a stream and read
+// back after that stream drains, so that many handles share one wait
+constexpr unsigned kHistBigPrefix = 1024;  // large sizes copied back with the histogram
+bool hist_cached(const kk_sim* h, int species);
+kk_status hist_enqueue(kk_sim* h, int species, hipStream_t stream);
+kk_status hist_finish(kk_sim* h, int species);
 kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t n);
 
 // batch engine over borrowed handles (kk_batch.cpp), used by the job server:

@@ -31,6 +31,7 @@ EXPORTS = [
     "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
+    "kk_batch_cluster_hists",
     "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
@@ -146,6 +147,7 @@ def load(path: str = LIB_PATH):
         "kk_batch_create": [PP, ctypes.POINTER(Replica), ctypes.c_size_t, P],
         "kk_batch_run": [P],
         "kk_batch_sim": [P, ctypes.c_size_t, PP],
+        "kk_batch_cluster_hists": [P, ctypes.c_int],
         "kk_batch_info": [P, szp, szp, szp],
         "kk_batch_autotune": [P, U32, u32p, u32p, dp],
         "kk_tri_batch_create": [PP, ctypes.POINTER(TriReplica), ctypes.c_size_t, P],
@@ -396,6 +398,11 @@ class Batch:
         _check(load().kk_batch_sim(self._h, i, ctypes.byref(h)))
         j = self.jobs[i]
         return _Borrowed(h, j.L, float(j.omega), j.seed)
+
+    def cluster_hists(self, species: int = 1) -> None:
+        """Label every replica's clusters of `species` with one device wait; the
+        histograms are then returned by sim(i).cluster_hist(species)."""
+        _check(load().kk_batch_cluster_hists(self._h, species))
 
     def autotune(self, trial_sweeps: int = 10) -> Tuple[int, int, float]:
         """Pick the tile size of the tiled replicas by timing; returns (words, rows, ms_per_sweep)."""
