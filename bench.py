@@ -97,8 +97,8 @@ def roofline_alu(mix, weights, attempts_per_s):
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
-PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3c57b42b495a0ff", "tile": (16, 128, 2),
-                    "bytes_per_launch": 4768477}
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "a23a14855c64d2d0", "tile": (16, 128, 2),
+                    "bytes_per_launch": 4721934}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
@@ -112,9 +112,9 @@ MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "0a358e4a29639be4", "tile": (2
 # The 400^2 int8 paths (profiles/halo_kernel_400_int8.md): the plain sweep
 # kernel with 2 x 16 tiles, and the batch tile kernel at the autotuner's 16 x 28
 # tiles, one unit per thread, over the 12 runs.
-GRID_PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3c57b42b495a0ff", "plain_tile": (2, 16, 1),
-                         "plain_bytes_per_launch": 879504, "batch_tile": (16, 28),
-                         "batch_bytes_per_launch": 6703798}
+GRID_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a23a14855c64d2d0", "plain_tile": (2, 16, 1),
+                         "plain_bytes_per_launch": 886875, "batch_tile": (16, 28),
+                         "batch_bytes_per_launch": 6599878}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
@@ -485,11 +485,13 @@ def batched_vs_plain(sweeps: int, plain_sweeps: int, offgrid: bool = False):
             "plain_s": tp, "speedup": batched_rate / plain_rate, "plan": info}
 
 
-def grid_400(rounds: int, every: int, weights=None):
+def grid_400(rounds: int, every: int, weights=None, tile=None):
     """The 12-run 400x400 grid (3 compositions x 4 omegas, int8) advanced together
     in one batch, with every run's species-1 cluster histogram taken every
     `every` sweeps, against the same runs advanced one after another; and the
-    rooflines of the plain single-lattice sweep kernel and of the batch."""
+    rooflines of the plain single-lattice sweep kernel and of the batch.
+    `tile` (words, rows, units per thread) fixes the batch tile instead of
+    autotuning it, so that profiler runs all time the same tile."""
     import torch
 
     from paper_1309_4349_amd import kk
@@ -498,7 +500,11 @@ def grid_400(rounds: int, every: int, weights=None):
     jobs = wl.grid_400(sweeps=every)
     sites = sum(j.L * j.L for j in jobs)
     b = kk.Batch(jobs)
-    tw, th, _ = b.autotune(20)
+    if tile:
+        b.set_tile(*tile)
+        tw, th = tile[0], tile[1]
+    else:
+        tw, th, _ = b.autotune(20)
     plan = b.info()
     b.run()
     b.cluster_hists(1)
@@ -611,6 +617,8 @@ def main():
     ap.add_argument("--no-mpkk", action="store_true", help="skip the literal-MPKK measurement")
     ap.add_argument("--mpkk-steps", type=int, default=500, help="MPKK steps of the 4098 x 4095 ring")
     ap.add_argument("--mpkk-bias-steps", type=int, default=6000, help="measured steps per bias run (0 skips the bias runs)")
+    ap.add_argument("--grid-tile", default="",
+                    help="words,rows,units_per_thread: fix the 400^2 batch tile instead of autotuning it")
     ap.add_argument("--grid-only", action="store_true",
                     help="only the 400^2 grid measurement (its JSON on one line), for profiling that path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -653,7 +661,8 @@ def main():
     log(f"[bench] VALU issue cycles per wave64 instruction: {cycles}")
 
     if args.grid_only:
-        print(json.dumps({"grid_400": grid_400(args.grid_rounds, 1000, weights)}), flush=True)
+        tile = tuple(int(v) for v in args.grid_tile.split(",")) if args.grid_tile else None
+        print(json.dumps({"grid_400": grid_400(args.grid_rounds, 1000, weights, tile)}), flush=True)
         return
 
     job = wl.big_4096(args.sweeps)

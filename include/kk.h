@@ -354,6 +354,13 @@ kk_status kk_batch_cluster_hists(kk_batch *b, int species);
 kk_status kk_batch_autotune(kk_batch *b, uint32_t trial_sweeps, uint32_t *tile_words, uint32_t *tile_rows,
                             double *ms_per_sweep);
 
+/* Set the tile caps of the tiled replicas by hand (words 8 or 16; rows even,
+ * at most 128; 1 or 2 units per thread; a tile of (rows + 28) / 2 row pairs
+ * of words + 2 words must fit 512 threads times the units per thread) and
+ * re-plan, e.g. to repeat a tile that kk_batch_autotune chose.  Results never
+ * depend on the tile.  KK_EINVAL for a cap outside these limits. */
+kk_status kk_batch_set_tile(kk_batch *b, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread);
+
 /* How the batch runs: resident replicas, tiled replicas, tile jobs per sweep. */
 kk_status kk_batch_info(kk_batch *b, size_t *n_resident, size_t *n_tiled, size_t *n_tile_jobs);
 

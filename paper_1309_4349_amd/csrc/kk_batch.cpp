@@ -537,6 +537,20 @@ kk_status kk_batch_sim(kk_batch* b, size_t i, kk_sim** sim_out) {
   return KK_OK;
 }
 
+kk_status kk_batch_set_tile(kk_batch* b, uint32_t tile_words, uint32_t tile_rows, uint32_t units_per_thread) {
+  if (!b) return set_error(KK_EINVAL, "NULL batch");
+  if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");
+  if (tile_rows % 2 != 0 || tile_words > 16 || tile_rows > (uint32_t)kBatchTh || units_per_thread > 2 ||
+      !batch_tile_fits((int)tile_words, (int)tile_rows, (int)units_per_thread))
+    return set_error(KK_EINVAL, "tile %u x %u at %u units per thread: words 8 or 16, rows even and at most %d, "
+                     "and (rows + 28) / 2 * (words + 2) at most %d * units per thread",
+                     tile_words, tile_rows, units_per_thread, kBatchTh, kBatchTileThreads);
+  b->tile_tww = (int)tile_words;
+  b->tile_th = (int)tile_rows;
+  b->tile_ku = (int)units_per_thread;
+  return batch_replan(b, b->sims, b->sweeps);
+}
+
 kk_status kk_batch_cluster_hists(kk_batch* b, int species) {
   if (!b) return set_error(KK_EINVAL, "NULL batch");
   if (b->poisoned) return set_error(KK_ESTATE, "batch poisoned by an earlier error");

@@ -31,7 +31,7 @@ EXPORTS = [
     "kk_set_tile", "kk_get_tile", "kk_autotune",
     "kk_stream", "kk_sweep_timed", "kk_destroy", "kk_last_error",
     "kk_batch_create", "kk_batch_run", "kk_batch_sim", "kk_batch_info", "kk_batch_autotune", "kk_batch_destroy",
-    "kk_batch_cluster_hists",
+    "kk_batch_cluster_hists", "kk_batch_set_tile",
     "kk_tri_batch_create", "kk_tri_batch_run", "kk_tri_batch_sim", "kk_tri_batch_info", "kk_tri_batch_destroy",
     "kk_server_create", "kk_server_now", "kk_server_submit", "kk_server_step", "kk_server_poll",
     "kk_server_job_hist", "kk_server_job_lattice", "kk_server_release", "kk_server_get_stats",
@@ -148,6 +148,7 @@ def load(path: str = LIB_PATH):
         "kk_batch_run": [P],
         "kk_batch_sim": [P, ctypes.c_size_t, PP],
         "kk_batch_cluster_hists": [P, ctypes.c_int],
+        "kk_batch_set_tile": [P, U32, U32, U32],
         "kk_batch_info": [P, szp, szp, szp],
         "kk_batch_autotune": [P, U32, u32p, u32p, dp],
         "kk_tri_batch_create": [PP, ctypes.POINTER(TriReplica), ctypes.c_size_t, P],
@@ -398,6 +399,10 @@ class Batch:
         _check(load().kk_batch_sim(self._h, i, ctypes.byref(h)))
         j = self.jobs[i]
         return _Borrowed(h, j.L, float(j.omega), j.seed)
+
+    def set_tile(self, words: int, rows: int, units_per_thread: int = 2) -> None:
+        """Fix the tile caps of the tiled replicas (what autotune would choose) and re-plan."""
+        _check(load().kk_batch_set_tile(self._h, words, rows, units_per_thread))
 
     def cluster_hists(self, species: int = 1) -> None:
         """Label every replica's clusters of `species` with one device wait; the

@@ -148,3 +148,27 @@ def test_batch_segregated_starts_match_the_oracle():
     bad = (kk.Replica * 1)(kk.Replica(64, kk.LAYOUT_INT8, 0.5, 0.7, 5, 3, 7))
     h = ctypes.c_void_p()
     assert kk.load().kk_batch_create(ctypes.byref(h), bad, 1, None) == kk.KK_EINVAL
+
+
+def test_batch_set_tile_pins_the_plan():
+    jobs = [wl.Job(L=L, composition=0.5, omega=0.9, seed=wl.job_seed(5, i), sweeps=11, layout="int8")
+            for i, L in enumerate((400, 404, 512))]
+    say("case batch with pinned tiles")
+    ref = kk.Batch(jobs)
+    ref.run()
+    want = [ref.sim(i).get_lattice() for i in range(len(jobs))]
+    ref.close()
+    for tile in [(16, 28, 1), (8, 72, 1), (8, 128, 2), (16, 84, 2)]:
+        b = kk.Batch(jobs)
+        b.set_tile(*tile)
+        assert b.info()["tiled"] == len(jobs)
+        b.run()
+        for i in range(len(jobs)):
+            assert np.array_equal(b.sim(i).get_lattice(), want[i]), (tile, i)
+        b.close()
+    b = kk.Batch(jobs)
+    for bad in [(12, 28, 1), (16, 27, 1), (16, 130, 2), (16, 84, 1), (8, 128, 3)]:
+        with pytest.raises(kk.KKError) as e:
+            b.set_tile(*bad)
+        assert e.value.status == kk.KK_EINVAL, bad
+    b.close()
