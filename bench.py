@@ -506,10 +506,13 @@ def grid_400(rounds: int, every: int, weights=None, tile=None):
     else:
         tw, th, _ = b.autotune(20)
     plan = b.info()
-    b.run()
-    b.cluster_hists(1)
-    for i in range(len(jobs)):
-        b.sim(i).cluster_hist(1)
+    # warm-up rounds: in a process that has loaded torch, the first few
+    # labelling rounds after the batch is built take several ms longer
+    for _ in range(4):
+        b.run()
+        b.cluster_hists(1)
+        for i in range(len(jobs)):
+            b.sim(i).cluster_hist(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(rounds):
@@ -604,7 +607,7 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=10_000, help="sweeps per replica in the batch run")
     ap.add_argument("--batch-plain-sweeps", type=int, default=500,
                     help="sweeps per replica for the one-at-a-time plain baseline")
-    ap.add_argument("--grid-rounds", type=int, default=5, help="rounds of 1000 sweeps for the 400^2 grid")
+    ap.add_argument("--grid-rounds", type=int, default=10, help="rounds of 1000 sweeps for the 400^2 grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the job-server trace replay")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the saturated serving trace")
     ap.add_argument("--serve-light-jobs", type=int, default=60, help="jobs of the below-saturation trace")

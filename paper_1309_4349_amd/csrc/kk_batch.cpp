@@ -39,6 +39,7 @@ constexpr int kMaxTileGroups = 4;
 constexpr int kCtlSlots = kMaxTileGroups + 2, kCtlSmall = kMaxTileGroups, kCtlLarge = kMaxTileGroups + 1;
 // tile workgroups that fill the device once (256 CUs, two per CU)
 constexpr size_t kFillWorkgroups = 512;
+constexpr int kHistStreams = 4;
 }
 
 struct kk_batch {
@@ -54,6 +55,9 @@ struct kk_batch {
   bool own_sB = false;
   hipEvent_t ev_upload = nullptr, ev_res = nullptr;
   hipStream_t tg_stream[kMaxTileGroups] = {};
+  // histogram streams, made on the first kk_batch_cluster_hists (kept apart
+  // from the streams the sweep graph runs on)
+  hipStream_t hist_stream[kHistStreams] = {};
   hipEvent_t tg_done[kMaxTileGroups] = {};
   // plan, rebuilt by batch_plan
   std::vector<int> resident, tiled;
@@ -129,6 +133,8 @@ void free_batch(kk_batch* b) {
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->sA) (void)hipStreamDestroy(b->sA);
   if (b->sC) (void)hipStreamDestroy(b->sC);
+  for (hipStream_t hs : b->hist_stream)
+    if (hs) (void)hipStreamDestroy(hs);
   if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
 }
 
@@ -560,23 +566,23 @@ kk_status kk_batch_cluster_hists(kk_batch* b, int species) {
     if (h->poisoned) return set_error(KK_ESTATE, "a replica is poisoned");
     if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
   }
-  // the labellings spread over the batch's streams (a small lattice's passes
-  // fill a fraction of the device), one wait per stream, then the read-back
-  hipStream_t streams[kMaxTileGroups + 3] = {b->sB, b->sA, b->sC};
-  int ns = 3;
-  for (int g = 0; g < kMaxTileGroups; ++g)
-    if (b->tg_stream[g]) streams[ns++] = b->tg_stream[g];
+  // the labellings spread over the histogram streams (a small lattice's
+  // passes fill a fraction of the device), one wait per stream, then the
+  // read-back.  (Spreading them over the sweep graph's own streams made the
+  // next run slower.)
+  for (hipStream_t& hs : b->hist_stream)
+    if (!hs) KB_HIP(hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
   std::vector<kk_sim*> todo;
   for (kk_sim* h : b->sims) {
     if (hist_cached(h, species)) continue;
-    const kk_status st = hist_enqueue(h, species, streams[todo.size() % ns]);
+    const kk_status st = hist_enqueue(h, species, b->hist_stream[todo.size() % kHistStreams]);
     if (st != KK_OK) {
       b->poisoned = true;
       return st;
     }
     todo.push_back(h);
   }
-  for (int i = 0; i < ns; ++i) KB_HIP(hipStreamSynchronize(streams[i]));
+  for (hipStream_t hs : b->hist_stream) KB_HIP(hipStreamSynchronize(hs));
   for (kk_sim* h : todo) {
     const kk_status st = hist_finish(h, species);
     if (st != KK_OK) return st;
@@ -599,6 +605,8 @@ void kk_batch_destroy(kk_batch* b) {
   if (b->sC) (void)hipStreamSynchronize(b->sC);
   for (int g = 0; g < kMaxTileGroups; ++g)
     if (b->tg_stream[g]) (void)hipStreamSynchronize(b->tg_stream[g]);
+  for (hipStream_t hs : b->hist_stream)
+    if (hs) (void)hipStreamSynchronize(hs);
   free_batch(b);
   delete b;
 }
