@@ -279,48 +279,82 @@ __device__ __forceinline__ void tri_tile_body(const uint8_t* __restrict__ in, ui
   const uint32_t lane_ring = lane * L, lane_win = lane * S;
   const uint32_t wave_u = __builtin_amdgcn_readfirstlane(wave);
   unsigned long long cnt = 0;
-  for (int p = 0; p < 16; ++p) {
-    const uint32_t cls = perm_s[p];
-    const uint32_t lo = 2u * (uint32_t)p + 2u;
-    const uint32_t rhi = WR - lo, chi = WC - lo;
-    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 15u) >> 4;
-    for (uint32_t it = wave_u; it < nrg * Q; it += nwaves) {
-      const uint32_t rg = it / Q, q = it - rg * Q;
-      const uint32_t r0 = lo + rg * 64u;  // uniform first row of the item
-      const uint32_t r = r0 + lane;
-      if (r >= rhi) continue;
-      uint32_t rb0 = base + r0 * L;
-      rb0 = rb0 >= N ? rb0 - N : rb0;
-      uint32_t rb = rb0 + lane_ring;
-      rb = rb >= N ? rb - N : rb;
-      const uint32_t c = lo + ((cls - rb - lo) & 15u) + 16u * q;
-      if (c >= chi) continue;
-      uint32_t i = rb + c;
-      i = i >= N ? i - N : i;
-      const Philox4 rr = philox10(i >> 1, 0u, tl, th, k0, k1);
-      const uint32_t wd = (i & 1u) ? rr.z : rr.x, u = (i & 1u) ? rr.w : rr.y;
-      const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
-      const uint32_t a = r0 * S + lane_win + c;
+  // this wave's ring of pending centres: the pair's window cell a, direction,
+  // a's species and whether the centre lies in the tile, then the uniform u
+  uint2* ring = reinterpret_cast<uint2*>(win + tri_window_area(TW, TR)) + wave * kTriQueue;
+  auto site = [&](uint32_t k) {  // sites hold 0 or 1, so x ^ v counts an unlike neighbour
+    const uint32_t x = win[k];
+    __builtin_assume(x <= 1u);
+    return x;
+  };
+  // decide the first k pending centres of the ring (lanes below k)
+  auto decide = [&](uint32_t head, uint32_t k) {
+    if (lane < k) {
+      const uint2 e = ring[(head + lane) & (kTriQueue - 1u)];
+      const uint32_t a = e.x & 0xFFFFFu, d = (e.x >> 20) & 7u, va = (e.x >> 23) & 1u, vb = va ^ 1u;
       const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
       const uint32_t b = (d & 1u) ? a - mag : a + mag;
-      // sites hold 0 or 1, so x ^ v counts an unlike neighbour
-      auto site = [&](uint32_t k) {
-        const uint32_t x = win[k];
-        __builtin_assume(x <= 1u);
-        return x;
-      };
-      const uint32_t va = site(a), vb = site(b);
-      if (va == vb) continue;
       // the a-b bond is unlike and appears once in each neighbourhood
       const uint32_t n = (site(a + 1) ^ va) + (site(a - 1) ^ va) + (site(a + S) ^ va) + (site(a - S) ^ va) +
                          (site(a + S - 1) ^ va) + (site(a - S + 1) ^ va) + (site(b + 1) ^ vb) + (site(b - 1) ^ vb) +
                          (site(b + S) ^ vb) + (site(b - S) ^ vb) + (site(b + S - 1) ^ vb) + (site(b - S + 1) ^ vb) -
                          2u;
-      if (u < thr_s[n] || ((always >> n) & 1u)) {
+      if (e.y < thr_s[n] || ((always >> n) & 1u)) {
         win[a] = (uint8_t)vb;
         win[b] = (uint8_t)va;
-        cnt += (r - kTriHalo < TRe) & (c - kTriHalo < TWe);
+        cnt += (e.x >> 24) & 1u;
       }
+    }
+  };
+  for (int p = 0; p < 16; ++p) {
+    const uint32_t cls = perm_s[p];
+    const uint32_t lo = 2u * (uint32_t)p + 2u;
+    const uint32_t rhi = WR - lo, chi = WC - lo;
+    const uint32_t nrg = (rhi - lo + 63u) >> 6, Q = (chi - lo + 15u) >> 4;
+    // Centres of one class never share a site or a neighbourhood, so their
+    // decisions may run in any order: a wave draws the random numbers of 64
+    // centres, queues those whose pair is unlike (a fraction of them once the
+    // lattice has ordered) and decides 64 queued centres at a time.
+    uint32_t qhead = 0, qtail = 0;  // uniform
+    for (uint32_t it = wave_u; it < nrg * Q; it += nwaves) {
+      const uint32_t rg = it / Q, q = it - rg * Q;
+      const uint32_t r0 = lo + rg * 64u;  // uniform first row of the item
+      const uint32_t r = r0 + lane;
+      uint32_t rb0 = base + r0 * L;
+      rb0 = rb0 >= N ? rb0 - N : rb0;
+      uint32_t rb = rb0 + lane_ring;
+      rb = rb >= N ? rb - N : rb;
+      const uint32_t c = lo + ((cls - rb - lo) & 15u) + 16u * q;
+      const bool ok = r < rhi && c < chi;
+      uint32_t i = rb + c;
+      i = i >= N ? i - N : i;
+      const Philox4 rr = philox10(i >> 1, 0u, tl, th, k0, k1);
+      const uint32_t wd = (i & 1u) ? rr.z : rr.x, u = (i & 1u) ? rr.w : rr.y;
+      const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
+      // a lane past the phase's region looks at window cell (1, 1) and its
+      // neighbour, inside the window, and queues nothing
+      const uint32_t a = ok ? r0 * S + lane_win + c : S + 1u;
+      const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
+      const uint32_t b = (d & 1u) ? a - mag : a + mag;
+      const uint32_t va = site(a), vb = site(b);
+      const bool live = ok && va != vb;
+      const uint64_t m = __ballot(live);
+      if (m == 0) continue;
+      if (live) {
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const uint32_t counted = (r - kTriHalo < TRe) & (c - kTriHalo < TWe);
+        ring[(qtail + pos) & (kTriQueue - 1u)] = make_uint2(a | (d << 20) | (va << 23) | (counted << 24), u);
+      }
+      qtail += (uint32_t)__popcll(m);
+      if (qtail - qhead >= 64u) {  // at most 127 pending: the ring never overflows
+        decide(qhead, 64u);
+        qhead += 64u;
+      }
+    }
+    while (qtail != qhead) {
+      const uint32_t k = min(qtail - qhead, 64u);
+      decide(qhead, k);
+      qhead += k;
     }
     __syncthreads();
   }

@@ -22,8 +22,15 @@ __host__ __device__ inline uint32_t tri_window_stride(uint32_t TW) {
   const uint32_t s = (TW + 2 * kTriHalo + 3u) & ~3u;  // whole words, an odd number of them
   return ((s >> 2) & 1u) ? s : s + 4u;
 }
+// Per workgroup, after the window: each of the 16 waves keeps a ring of 128
+// pending centres (8 bytes each) whose pair is unlike, so that the decisions
+// run on full waves (tri_tile_sweep).
+constexpr uint32_t kTriQueue = 128, kTriQueueBytes = 16u * kTriQueue * 8u;
+__host__ __device__ inline size_t tri_window_area(uint32_t TW, uint32_t TR) {
+  return ((size_t)tri_window_stride(TW) * (TR + 2 * kTriHalo) + 7u) & ~(size_t)7u;
+}
 __host__ __device__ inline size_t tri_window_bytes(uint32_t TW, uint32_t TR) {
-  return (size_t)tri_window_stride(TW) * (TR + 2 * kTriHalo);
+  return tri_window_area(TW, TR) + kTriQueueBytes;
 }
 inline bool tri_tile_fits(int L, int H, int TW, int TR) {
   return TW >= 16 && TR >= 16 && TW + 2 * (int)kTriHalo <= L && TR + 2 * (int)kTriHalo <= H &&
