@@ -553,9 +553,32 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
   uint32_t* win32 = reinterpret_cast<uint32_t*>(win);
   const uint32_t nwords = (S >> 2) * WR;
   unsigned long long cnt = 0;
+  // this wave's ring of pending attempts whose pair is unlike (domains are
+  // disjoint and every read uses the start-of-iteration bit, so the order of
+  // the decisions does not matter): cell a, direction, a's species and whether
+  // the centre lies in the tile, then the uniform u
+  uint2* ring = reinterpret_cast<uint2*>(win + mpkk_window_area(TW, TR)) + wave * kTriQueue;
+  auto decide = [&](uint32_t head, uint32_t kq) {
+    if (lane < kq) {
+      const uint2 e = ring[(head + lane) & (kTriQueue - 1u)];
+      const uint32_t a = e.x & 0xFFFFFu, d = (e.x >> 20) & 7u, va = (e.x >> 23) & 1u, vb = va ^ 1u;
+      const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
+      const uint32_t b = (d & 1u) ? a - mag : a + mag;
+      const uint32_t n = ((win[a + 1] ^ va) & 1u) + ((win[a - 1] ^ va) & 1u) + ((win[a + S] ^ va) & 1u) +
+                         ((win[a - S] ^ va) & 1u) + ((win[a + S - 1] ^ va) & 1u) + ((win[a - S + 1] ^ va) & 1u) +
+                         ((win[b + 1] ^ vb) & 1u) + ((win[b - 1] ^ vb) & 1u) + ((win[b + S] ^ vb) & 1u) +
+                         ((win[b - S] ^ vb) & 1u) + ((win[b + S - 1] ^ vb) & 1u) + ((win[b - S + 1] ^ vb) & 1u) - 2u;
+      if (e.y < thr_s[n] || ((always >> n) & 1u)) {
+        win[a] = (uint8_t)(va | 2u);
+        win[b] = (uint8_t)(vb | 2u);
+        cnt += (e.x >> 24) & 1u;
+      }
+    }
+  };
   for (int j = 0; j < 7; ++j) {
     const uint32_t k = k_s[j];
     const uint32_t lo = 3u * (uint32_t)j + 2u;
+    uint32_t qhead = 0, qtail = 0;  // uniform
     const uint32_t rhi = WR - lo, chi = WC - lo;
     // A work item is a lane's pair of consecutive domains m, m + 1 along its
     // row (7 sites apart) with m even: both take their numbers from Philox
@@ -567,7 +590,7 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
       const uint32_t rg = it / Q, q = it - rg * Q;
       const uint32_t r0 = lo + rg * 64u;
       const uint32_t r = r0 + lane;
-      if (r >= rhi) continue;
+      const bool rok = r < rhi;
       uint32_t rb0 = base + r0 * L;
       rb0 = rb0 >= N ? rb0 - N : rb0;
       uint32_t rb = rb0 + lane_ring;
@@ -579,8 +602,7 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
       const uint32_t mf = (i_f - k) / 7u;
       // the item's second centre (never before cf) and first centre
       const uint32_t c2 = cf + 7u * (1u - (mf & 1u)) + 14u * q;
-      const bool ok1 = c2 >= lo + 7u && c2 - 7u < chi, ok2 = c2 < chi;
-      if (!ok1 && !ok2) continue;
+      const bool ok1 = rok && c2 >= lo + 7u && c2 - 7u < chi, ok2 = rok && c2 < chi;
       uint32_t i2 = rb + c2;
       i2 = i2 >= N ? i2 - N : i2;
       const uint32_t i1 = i2 >= 7u ? i2 - 7u : i2 + N - 7u;
@@ -589,27 +611,38 @@ __global__ __launch_bounds__(1024) void mpkk_tile_step(const uint8_t* __restrict
       Philox4 r2 = r1;
       if ((m2 >> 1) != (m1 >> 1)) r2 = philox10(m2 >> 1, (uint32_t)j, tl, th, k0, k1);
       const uint32_t rowa = r0 * S + lane_win;
-      // one domain: centre at column c, direction word wd, uniform u
-      auto attempt = [&](uint32_t c, uint32_t wd, uint32_t u) {
+      // one domain: centre at column c, direction word wd, uniform u; queued
+      // when its pair is unlike (every lane takes part in the ballot)
+      auto attempt = [&](bool ok, uint32_t c, uint32_t wd, uint32_t u) {
         const uint32_t d = (uint32_t)(((uint64_t)wd * 6u) >> 32);
-        const uint32_t a = rowa + c;
+        // a lane without this domain looks at window cell (1, 1) and its neighbour
+        const uint32_t a = ok ? rowa + c : S + 1u;
         const uint32_t mag = d < 2 ? 1u : (d < 4 ? S : S - 1u);
         const uint32_t b = (d & 1u) ? a - mag : a + mag;
         // bit 0 of a byte is the value at the start of the iteration
         const uint32_t va = win[a] & 1u, vb = win[b] & 1u;
-        if (va == vb) return;
-        const uint32_t n = ((win[a + 1] ^ va) & 1u) + ((win[a - 1] ^ va) & 1u) + ((win[a + S] ^ va) & 1u) +
-                           ((win[a - S] ^ va) & 1u) + ((win[a + S - 1] ^ va) & 1u) + ((win[a - S + 1] ^ va) & 1u) +
-                           ((win[b + 1] ^ vb) & 1u) + ((win[b - 1] ^ vb) & 1u) + ((win[b + S] ^ vb) & 1u) +
-                           ((win[b - S] ^ vb) & 1u) + ((win[b + S - 1] ^ vb) & 1u) + ((win[b - S + 1] ^ vb) & 1u) - 2u;
-        if (u < thr_s[n] || ((always >> n) & 1u)) {
-          win[a] = (uint8_t)(va | 2u);
-          win[b] = (uint8_t)(vb | 2u);
-          cnt += (r - kMpkkHalo < TRe) & (c - kMpkkHalo < TWe);
+        const bool live = ok && va != vb;
+        const uint64_t mk = __ballot(live);
+        if (mk == 0) return;
+        if (live) {
+          const uint32_t pos =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+          const uint32_t counted = (r - kMpkkHalo < TRe) & (c - kMpkkHalo < TWe);
+          ring[(qtail + pos) & (kTriQueue - 1u)] = make_uint2(a | (d << 20) | (va << 23) | (counted << 24), u);
+        }
+        qtail += (uint32_t)__popcll(mk);
+        if (qtail - qhead >= 64u) {  // at most 127 pending: the ring never overflows
+          decide(qhead, 64u);
+          qhead += 64u;
         }
       };
-      if (ok1) attempt(c2 - 7u, (m1 & 1u) ? r1.z : r1.x, (m1 & 1u) ? r1.w : r1.y);
-      if (ok2) attempt(c2, (m2 & 1u) ? r2.z : r2.x, (m2 & 1u) ? r2.w : r2.y);
+      attempt(ok1, c2 - 7u, (m1 & 1u) ? r1.z : r1.x, (m1 & 1u) ? r1.w : r1.y);
+      attempt(ok2, c2, (m2 & 1u) ? r2.z : r2.x, (m2 & 1u) ? r2.w : r2.y);
+    }
+    while (qtail != qhead) {
+      const uint32_t kk = min(qtail - qhead, 64u);
+      decide(qhead, kk);
+      qhead += kk;
     }
     __syncthreads();
     // fold the flips: value ^= flip, four bytes at a time

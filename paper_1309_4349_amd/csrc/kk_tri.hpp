@@ -77,8 +77,13 @@ __host__ __device__ inline uint32_t mpkk_window_stride(uint32_t TW) {
   const uint32_t s = (TW + 2 * kMpkkHalo + 3u) & ~3u;  // whole words, an odd number of them
   return ((s >> 2) & 1u) ? s : s + 4u;
 }
+// The window, then the per-wave rings of pending attempts (as for the class
+// schedule's tile kernel).
+__host__ __device__ inline size_t mpkk_window_area(uint32_t TW, uint32_t TR) {
+  return ((size_t)mpkk_window_stride(TW) * (TR + 2 * kMpkkHalo) + 15u) & ~(size_t)15u;
+}
 __host__ __device__ inline size_t mpkk_window_bytes(uint32_t TW, uint32_t TR) {
-  return (size_t)mpkk_window_stride(TW) * (TR + 2 * kMpkkHalo);
+  return mpkk_window_area(TW, TR) + kTriQueueBytes;
 }
 inline bool mpkk_tile_fits(int L, int H, int TW, int TR) {
   return TW >= 16 && TR >= 16 && TW + 2 * (int)kMpkkHalo <= L && TR + 2 * (int)kMpkkHalo <= H &&
