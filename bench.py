@@ -102,13 +102,13 @@ PROFILED_TRAFFIC = {"sources_sha256_prefix": "a23a14855c64d2d0", "tile": (16, 12
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
-TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "748737f2f478465e", "tile": (256, 256),
-                        "bytes_per_launch": 35862799}
+TRI_PROFILED_TRAFFIC = {"sources_sha256_prefix": "acfed7f9645a8c30", "tile": (256, 256),
+                        "bytes_per_launch": 35863064}
 TRI_KERNEL_SOURCES = ["kk_tri.hip", "kk_tri.hpp", "kk_common.hpp"]
 # And for the literal-MPKK whole-step tile kernel on the 4098 x 4095 ring with
 # 257 x 256 tiles (profiles/mpkk_tile_step_4098x4095.md).
-MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "748737f2f478465e", "tile": (257, 256),
-                         "bytes_per_launch": 35115218}
+MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "acfed7f9645a8c30", "tile": (257, 256),
+                         "bytes_per_launch": 35132607}
 # The 400^2 int8 paths (profiles/halo_kernel_400_int8.md): the plain sweep
 # kernel with 2 x 16 tiles, and the batch tile kernel at the autotuner's 16 x 28
 # tiles, one unit per thread, over the 12 runs.
