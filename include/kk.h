@@ -145,8 +145,9 @@ kk_status kk_create_triangular_ex(kk_sim **out, uint32_t L, uint32_t H, uint32_t
  * Results do not depend on the choice (the window carries every exchange that
  * can reach the tile within the launch).  Needs cols, rows >= 16,
  * cols + 2h <= L, rows + 2h <= H (h = 33, or 21 for MPKK) and a window of at
- * most 159 KiB ((cols + 2h, rounded up to an odd number of 4-byte words) x
- * (rows + 2h) bytes); KK_EINVAL otherwise and on square handles.  On the
+ * most 143 KiB ((cols + 2h, rounded up to an odd number of 4-byte words) x
+ * (rows + 2h) bytes; the workgroup also keeps 16 KiB of queued attempts);
+ * KK_EINVAL otherwise and on square handles.  On the
  * class schedule, cols = L and rows = H selects the whole ring in one
  * workgroup's LDS (no halo, up to 1024 sweeps per launch, in place; needs
  * L * H <= 159 KiB).  The default is the tile of least modelled time,
