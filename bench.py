@@ -97,8 +97,8 @@ def roofline_alu(mix, weights, attempts_per_s):
 # profiles/halo_kernel_4096_bitpacked.md (counters scaled by what they read for
 # a plain copy kernel of known size).  Valid only for the kernel sources that
 # were profiled: the line reports null once they change.
-PROFILED_TRAFFIC = {"sources_sha256_prefix": "a23a14855c64d2d0", "tile": (16, 128, 2),
-                    "bytes_per_launch": 4721934}
+PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3cfdf93ff201d3a", "tile": (16, 128, 2),
+                    "bytes_per_launch": 4721976}
 KERNEL_SOURCES = ["kk_sweep.hip", "kk_common.hpp", "kk_kernels.hpp"]
 # The same for the triangular whole-sweep tile kernel on the 4092^2 lattice with
 # 256 x 256 tiles (profiles/tri_tile_sweep_4092.md).
@@ -112,9 +112,9 @@ MPKK_PROFILED_TRAFFIC = {"sources_sha256_prefix": "acfed7f9645a8c30", "tile": (2
 # The 400^2 int8 paths (profiles/halo_kernel_400_int8.md): the plain sweep
 # kernel with 2 x 16 tiles, and the batch tile kernel at the autotuner's 16 x 28
 # tiles, one unit per thread, over the 12 runs.
-GRID_PROFILED_TRAFFIC = {"sources_sha256_prefix": "a23a14855c64d2d0", "plain_tile": (2, 16, 1),
-                         "plain_bytes_per_launch": 886875, "batch_tile": (16, 28),
-                         "batch_bytes_per_launch": 6599878}
+GRID_PROFILED_TRAFFIC = {"sources_sha256_prefix": "b3cfdf93ff201d3a", "plain_tile": (2, 16, 1),
+                         "plain_bytes_per_launch": 886838, "batch_tile": (16, 28),
+                         "batch_bytes_per_launch": 6599810}
 
 
 def kernel_sources_sha(files=KERNEL_SOURCES) -> str:
