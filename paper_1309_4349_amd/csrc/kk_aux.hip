@@ -2,6 +2,7 @@
 // conversion kernels of libkk.
 #include "kk_common.hpp"
 #include "kk_kernels.hpp"
+#include "kk_ccl.hpp"
 
 namespace kk {
 
@@ -192,9 +193,8 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
 
 // Also clears what the later passes accumulate into: the cluster sizes, the
 // small-size histogram and the count of large sizes.
-__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species,
-                                                uint32_t* parent, uint32_t* size, unsigned* hist,
-                                                unsigned* big_count) {
+__device__ __forceinline__ void ccl_init_body(const void* lat, int layout, int L, int H, int species,
+                                              uint32_t* parent, uint32_t* size, unsigned* hist, unsigned* big_count) {
   const size_t n = (size_t)L * H;
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, nth = (size_t)gridDim.x * blockDim.x;
   for (size_t i = tid; i < n; i += nth) {
@@ -206,8 +206,7 @@ __global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int
   if (tid == 0) *big_count = 0u;
 }
 
-__global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, int L, int species,
-                                                 uint32_t* parent) {
+__device__ __forceinline__ void ccl_merge_body(const void* lat, int layout, int L, int species, uint32_t* parent) {
   const size_t n = (size_t)L * L;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(256) void ccl_merge_tri(const uint8_t* lat, int L, 
 }
 
 // After all unions: point every site straight at its root.
-__global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L, int H) {
+__device__ __forceinline__ void ccl_flatten_body(uint32_t* parent, int L, int H) {
   const size_t n = (size_t)L * H;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     if (ld_parent(parent, (uint32_t)i) == kNone) continue;
@@ -266,7 +265,7 @@ __global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L, int 
 // Cluster sizes (parents flattened): one add per site onto its root, aggregated over the
 // wavefront first (lanes with the same root add once, by their lowest lane),
 // so a spanning cluster costs one atomic per wave instead of one per site.
-__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, int H, uint32_t* size) {
+__device__ __forceinline__ void ccl_count_body(uint32_t* parent, int L, int H, uint32_t* size) {
   const size_t n = (size_t)L * H;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const int lane = (int)__lane_id();
@@ -287,9 +286,8 @@ __global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, int H,
   }
 }
 
-__global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, int H, unsigned* hist, uint32_t* big,
-                                                unsigned* big_count, unsigned big_cap) {
-  __shared__ unsigned h[kSmallSizes];
+__device__ __forceinline__ void ccl_hist_body(const uint32_t* size, int L, int H, unsigned* hist, uint32_t* big,
+                                              unsigned* big_count, unsigned big_cap, unsigned* h) {
   for (int k = threadIdx.x; k < kSmallSizes; k += blockDim.x) h[k] = 0;
   __syncthreads();
   const size_t n = (size_t)L * H;
@@ -305,6 +303,56 @@ __global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, int
   __syncthreads();
   for (int k = threadIdx.x; k < kSmallSizes; k += blockDim.x)
     if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// The passes as kernels for one lattice (grid-stride over blockIdx.x), and
+// for many square lattices at once: replica blockIdx.y of a table, each with
+// its own buffers, the same grid-stride over blockIdx.x.
+__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species,
+                                                uint32_t* parent, uint32_t* size, unsigned* hist,
+                                                unsigned* big_count) {
+  ccl_init_body(lat, layout, L, H, species, parent, size, hist, big_count);
+}
+__global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, int L, int species, uint32_t* parent) {
+  ccl_merge_body(lat, layout, L, species, parent);
+}
+__global__ __launch_bounds__(256) void ccl_flatten(uint32_t* parent, int L, int H) { ccl_flatten_body(parent, L, H); }
+__global__ __launch_bounds__(256) void ccl_count(uint32_t* parent, int L, int H, uint32_t* size) {
+  ccl_count_body(parent, L, H, size);
+}
+__global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, int H, unsigned* hist, uint32_t* big,
+                                                unsigned* big_count, unsigned big_cap) {
+  __shared__ unsigned h[kSmallSizes];
+  ccl_hist_body(size, L, H, hist, big, big_count, big_cap, h);
+}
+__global__ __launch_bounds__(256) void ccl_init_many(const CclRep* reps, int species) {
+  const CclRep& r = reps[blockIdx.y];
+  ccl_init_body(r.lat, r.layout, r.L, r.L, species, r.b.parent, r.b.size, r.b.hist, r.b.big_count);
+}
+__global__ __launch_bounds__(256) void ccl_merge_many(const CclRep* reps, int species) {
+  const CclRep& r = reps[blockIdx.y];
+  ccl_merge_body(r.lat, r.layout, r.L, species, r.b.parent);
+}
+__global__ __launch_bounds__(256) void ccl_flatten_many(const CclRep* reps) {
+  const CclRep& r = reps[blockIdx.y];
+  ccl_flatten_body(r.b.parent, r.L, r.L);
+}
+__global__ __launch_bounds__(256) void ccl_count_many(const CclRep* reps) {
+  const CclRep& r = reps[blockIdx.y];
+  ccl_count_body(r.b.parent, r.L, r.L, r.b.size);
+}
+__global__ __launch_bounds__(256) void ccl_hist_many(const CclRep* reps) {
+  __shared__ unsigned h[kSmallSizes];
+  const CclRep& r = reps[blockIdx.y];
+  ccl_hist_body(r.b.size, r.L, r.L, r.b.hist, r.b.big, r.b.big_count, r.b.big_cap, h);
+}
+// Every replica's result block (histogram, large-size count, first large
+// sizes) into row blockIdx.y of one staging array of `words` per replica.
+__global__ __launch_bounds__(256) void ccl_gather_many(const CclRep* reps, uint32_t* stage, uint32_t words) {
+  const CclRep& r = reps[blockIdx.y];
+  const uint32_t n = min(words, (uint32_t)kSmallSizes + 1u + r.b.big_cap);
+  uint32_t* dst = stage + (size_t)blockIdx.y * words;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = r.b.hist[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +443,20 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, co
   // them adds into the hot small sizes: few workgroups, each streaming many sites
   hipLaunchKernelGGL(ccl_hist, dim3(g < 128 ? g : 128), dim3(256), 0, stream, b.size, L, H, b.hist, b.big,
                      b.big_count, b.big_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_ccl_many(const CclRep* d_reps, int nreps, size_t max_sites, int species, uint32_t* stage,
+                           uint32_t words, hipStream_t stream) {
+  if (nreps <= 0) return hipSuccess;
+  const int g = grid_for(max_sites, 256);
+  const dim3 grid((unsigned)g, (unsigned)nreps), hgrid((unsigned)(g < 128 ? g : 128), (unsigned)nreps);
+  hipLaunchKernelGGL(ccl_init_many, grid, dim3(256), 0, stream, d_reps, species);
+  hipLaunchKernelGGL(ccl_merge_many, grid, dim3(256), 0, stream, d_reps, species);
+  hipLaunchKernelGGL(ccl_flatten_many, grid, dim3(256), 0, stream, d_reps);
+  hipLaunchKernelGGL(ccl_count_many, grid, dim3(256), 0, stream, d_reps);
+  hipLaunchKernelGGL(ccl_hist_many, hgrid, dim3(256), 0, stream, d_reps);
+  hipLaunchKernelGGL(ccl_gather_many, dim3(8, (unsigned)nreps), dim3(256), 0, stream, d_reps, stage, words);
   return hipGetLastError();
 }
 

@@ -23,12 +23,14 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <new>
 #include <vector>
 
 #include "../../include/kk.h"
 #include "kk_host.hpp"
 #include "kk_kernels.hpp"
+#include "kk_ccl.hpp"
 
 using namespace kk;
 
@@ -39,7 +41,6 @@ constexpr int kMaxTileGroups = 4;
 constexpr int kCtlSlots = kMaxTileGroups + 2, kCtlSmall = kMaxTileGroups, kCtlLarge = kMaxTileGroups + 1;
 // tile workgroups that fill the device once (256 CUs, two per CU)
 constexpr size_t kFillWorkgroups = 512;
-constexpr int kHistStreams = 4;
 }
 
 struct kk_batch {
@@ -55,9 +56,11 @@ struct kk_batch {
   bool own_sB = false;
   hipEvent_t ev_upload = nullptr, ev_res = nullptr;
   hipStream_t tg_stream[kMaxTileGroups] = {};
-  // histogram streams, made on the first kk_batch_cluster_hists (kept apart
-  // from the streams the sweep graph runs on)
-  hipStream_t hist_stream[kHistStreams] = {};
+  // batched labelling (kk_batch_cluster_hists), made on first use: the table
+  // of lattices, the staging rows of the result blocks and their pinned image
+  CclRep* d_ccl = nullptr;
+  uint32_t* d_hist_stage = nullptr;
+  uint32_t* h_hist_stage = nullptr;
   hipEvent_t tg_done[kMaxTileGroups] = {};
   // plan, rebuilt by batch_plan
   std::vector<int> resident, tiled;
@@ -133,8 +136,9 @@ void free_batch(kk_batch* b) {
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->sA) (void)hipStreamDestroy(b->sA);
   if (b->sC) (void)hipStreamDestroy(b->sC);
-  for (hipStream_t hs : b->hist_stream)
-    if (hs) (void)hipStreamDestroy(hs);
+  if (b->d_ccl) (void)hipFree(b->d_ccl);
+  if (b->d_hist_stage) (void)hipFree(b->d_hist_stage);
+  if (b->h_hist_stage) (void)hipHostFree(b->h_hist_stage);
   if (b->own_sB && b->sB) (void)hipStreamDestroy(b->sB);
 }
 
@@ -566,23 +570,36 @@ kk_status kk_batch_cluster_hists(kk_batch* b, int species) {
     if (h->poisoned) return set_error(KK_ESTATE, "a replica is poisoned");
     if (h->stream != b->sB) KB_HIP(hipStreamSynchronize(h->stream));
   }
-  // the labellings spread over the histogram streams (a small lattice's
-  // passes fill a fraction of the device), one wait per stream, then the
-  // read-back.  (Spreading them over the sweep graph's own streams made the
-  // next run slower.)
-  for (hipStream_t& hs : b->hist_stream)
-    if (!hs) KB_HIP(hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
+  // every lattice that needs it labelled in one set of launches (replica =
+  // blockIdx.y), the result blocks gathered into one staging array, one copy
+  // and one wait
   std::vector<kk_sim*> todo;
+  std::vector<CclRep> reps;
+  size_t max_sites = 0;
   for (kk_sim* h : b->sims) {
     if (hist_cached(h, species)) continue;
-    const kk_status st = hist_enqueue(h, species, b->hist_stream[todo.size() % kHistStreams]);
-    if (st != KK_OK) {
-      b->poisoned = true;
-      return st;
-    }
+    const kk_status st = hist_buffers(h);
+    if (st != KK_OK) return st;
     todo.push_back(h);
+    reps.push_back(CclRep{h->lat[h->cur], h->layout, h->L, h->ccl});
+    max_sites = std::max(max_sites, (size_t)h->L * (size_t)h->L);
   }
-  for (hipStream_t hs : b->hist_stream) KB_HIP(hipStreamSynchronize(hs));
+  if (todo.empty()) return KK_OK;
+  const uint32_t words = (uint32_t)kSmallSizes + 1u + kHistBigPrefix;
+  const size_t n = b->sims.size();
+  if (!b->d_ccl) {
+    kk_status st = device_alloc((void**)&b->d_ccl, n * sizeof(CclRep));
+    if (st == KK_OK) st = device_alloc((void**)&b->d_hist_stage, n * words * sizeof(uint32_t));
+    if (st != KK_OK) return st;
+    KB_HIP(hipHostMalloc((void**)&b->h_hist_stage, n * words * sizeof(uint32_t), hipHostMallocDefault));
+  }
+  KB_HIP(hipMemcpyAsync(b->d_ccl, reps.data(), reps.size() * sizeof(CclRep), hipMemcpyHostToDevice, b->sB));
+  KB_HIP(launch_ccl_many(b->d_ccl, (int)reps.size(), max_sites, species, b->d_hist_stage, words, b->sB));
+  KB_HIP(hipMemcpyAsync(b->h_hist_stage, b->d_hist_stage, todo.size() * words * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, b->sB));
+  KB_HIP(hipStreamSynchronize(b->sB));
+  for (size_t i = 0; i < todo.size(); ++i)
+    std::memcpy(todo[i]->hist_host, b->h_hist_stage + i * words, words * sizeof(uint32_t));
   for (kk_sim* h : todo) {
     const kk_status st = hist_finish(h, species);
     if (st != KK_OK) return st;
@@ -605,8 +622,6 @@ void kk_batch_destroy(kk_batch* b) {
   if (b->sC) (void)hipStreamSynchronize(b->sC);
   for (int g = 0; g < kMaxTileGroups; ++g)
     if (b->tg_stream[g]) (void)hipStreamSynchronize(b->tg_stream[g]);
-  for (hipStream_t hs : b->hist_stream)
-    if (hs) (void)hipStreamSynchronize(hs);
   free_batch(b);
   delete b;
 }

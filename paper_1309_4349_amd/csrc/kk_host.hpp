@@ -75,6 +75,7 @@ kk_status device_alloc(void** p, size_t bytes);
 // back after that stream drains, so that many handles share one wait
 constexpr unsigned kHistBigPrefix = 1024;  // large sizes copied back with the histogram
 bool hist_cached(const kk_sim* h, int species);
+kk_status hist_buffers(kk_sim* h);  // the labelling buffers and the pinned image, made once
 kk_status hist_enqueue(kk_sim* h, int species, hipStream_t stream);
 kk_status hist_finish(kk_sim* h, int species);
 kk_status fold_accepted(kk_sim* h, const unsigned long long* dev_counts, size_t n);
