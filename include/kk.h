@@ -329,7 +329,9 @@ kk_status kk_batch_create(kk_batch **out, const kk_replica *reps, size_t n, void
 kk_status kk_batch_run(kk_batch *b);
 
 /* Borrow replica i's handle for queries (kk_get_lattice, kk_energy,
- * kk_cluster_hist, kk_stats, ...).  The batch owns it: do not destroy it. */
+ * kk_cluster_hist, kk_stats, ...).  kk_set_lattice on it between runs is
+ * allowed: every run starts from the handle's lattice and sweep counter.
+ * The batch owns it: do not destroy it. */
 kk_status kk_batch_sim(kk_batch *b, size_t i, kk_sim **sim_out);
 
 /* The cluster-size histogram of `species` (0 or 1) of every replica, the one

@@ -6,7 +6,8 @@ both species, and a later kk_cluster_hist on the replica must return it without
 relabelling.  A single handle's histogram copies the small sizes, the count of
 large clusters and the first large sizes back in one go; a lattice with more
 large clusters than that first copy holds takes the second copy, checked here
-against the closed form of a striped lattice."""
+against the closed form of a striped lattice, on a single handle and as one
+replica of a batch."""
 import sys
 
 import numpy as np
@@ -77,3 +78,41 @@ def test_more_large_clusters_than_the_first_copy():
     assert s.cluster_hist(1) == [(L, L // 2)]
     assert s.cluster_hist(0) == [(L, L // 2)]
     s.close()
+
+
+def test_batch_cluster_hists_with_some_replicas_held():
+    # replicas whose histogram is already held are left out of the labelling
+    # launches; the others' result rows must still land on their own handles
+    js = jobs()
+    say(f"case batch histograms, {len(js)} replicas, two held beforehand")
+    b = kk.Batch(js)
+    b.run()
+    held = {1: b.sim(1).cluster_hist(1), 5: b.sim(5).cluster_hist(1)}
+    b.cluster_hists(1)
+    for i in range(len(js)):
+        s = b.sim(i)
+        want = oracle.cluster_hist(s.get_lattice(), 1)
+        assert s.cluster_hist(1) == want, i
+        if i in held:
+            assert held[i] == want, i
+    b.close()
+
+
+def test_batch_replica_with_more_large_clusters_than_the_first_copy():
+    # the striped lattice of the single-handle case, as one replica of a batch
+    # beside an ordinary one: its histogram takes the second copy
+    L = 4160
+    js = [wl.Job(L=L, composition=0.5, omega=0.5, seed=wl.job_seed(92, 0), sweeps=1, layout="int8"),
+          wl.Job(L=96, composition=0.4, omega=0.7, seed=wl.job_seed(92, 1), sweeps=3, layout="int8")]
+    say(f"case batch with a striped {L}^2 replica")
+    b = kk.Batch(js)
+    b.run()
+    lat = np.zeros((L, L), dtype=np.uint8)
+    lat[:, 0::2] = 1
+    b.sim(0).set_lattice(lat, 1)
+    for species in (1, 0):
+        b.cluster_hists(species)
+        assert b.sim(0).cluster_hist(species) == [(L, L // 2)]
+        s = b.sim(1)
+        assert s.cluster_hist(species) == oracle.cluster_hist(s.get_lattice(), species)
+    b.close()
