@@ -9,6 +9,8 @@ namespace kk {
 namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// workgroups per replica in a many-lattice labelling pass (grid-stride beyond)
+constexpr int kCclManyBlocks = 512;
 
 __device__ __forceinline__ int site_bit(const void* lat, int layout, int L, int x, int y) {
   if (layout == kLayoutBits)
@@ -449,7 +451,10 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, co
 hipError_t launch_ccl_many(const CclRep* d_reps, int nreps, size_t max_sites, int species, uint32_t* stage,
                            uint32_t words, hipStream_t stream) {
   if (nreps <= 0) return hipSuccess;
-  const int g = grid_for(max_sites, 256);
+  // every pass strides over its lattice, so a replica needs no more
+  // workgroups than fill the device with the others; workgroups past a
+  // smaller replica's sites exit at once
+  const int g = std::min(grid_for(max_sites, 256), kCclManyBlocks);
   const dim3 grid((unsigned)g, (unsigned)nreps), hgrid((unsigned)(g < 128 ? g : 128), (unsigned)nreps);
   hipLaunchKernelGGL(ccl_init_many, grid, dim3(256), 0, stream, d_reps, species);
   hipLaunchKernelGGL(ccl_merge_many, grid, dim3(256), 0, stream, d_reps, species);
