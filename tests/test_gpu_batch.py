@@ -125,6 +125,13 @@ def test_batch_edge_cases_match_the_oracle(specs):
         assert np.array_equal(s.get_lattice(), ref), (i, j.L)
         assert s.stats() == (j.sweeps, j.sweeps * j.L * j.L, acc), (i, j.L)
         assert s.energy()[0] == oracle.energy(ref)
+    # the batched labelling on the same set: empty species, one cluster of the
+    # whole lattice, the smallest sides
+    for species in (1, 0):
+        b.cluster_hists(species)
+        for i, j in enumerate(jobs):
+            s = b.sim(i)
+            assert s.cluster_hist(species) == oracle.cluster_hist(s.get_lattice(), species), (species, i, j.L)
     b.close()
 
 
