@@ -193,15 +193,36 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b) {
   }
 }
 
-// Also clears what the later passes accumulate into: the cluster sizes, the
-// small-size histogram and the count of large sizes.
-__device__ __forceinline__ void ccl_init_body(const void* lat, int layout, int L, int H, int species,
+// With `runs` (the square torus), a site of the species starts linked
+// straight to the first site of its run: the longest stretch of sites of the
+// species that ends at it, lies in one row and in its 64-site segment (sites
+// 64k .. 64k + 63, one wavefront of the pass: two ballots find it).  The
+// merge pass then needs a horizontal union only at segment ends and across
+// the row's wrap, and the trees it starts from are one level deep.  Without
+// it every site of the species starts as its own root.  Also clears what the
+// later passes accumulate into: the cluster sizes, the small-size histogram
+// and the count of large sizes.
+__device__ __forceinline__ void ccl_init_body(const void* lat, int layout, int L, int H, int species, bool runs,
                                               uint32_t* parent, uint32_t* size, unsigned* hist, unsigned* big_count) {
   const size_t n = (size_t)L * H;
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x, nth = (size_t)gridDim.x * blockDim.x;
+  // the stride is a whole number of wavefronts, so lane l of a wavefront
+  // always holds a site i with i % 64 == l, and the lanes past n are the top ones
   for (size_t i = tid; i < n; i += nth) {
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
-    parent[i] = (site_bit(lat, layout, L, x, y) == species) ? (uint32_t)i : kNone;
+    const bool me = site_bit(lat, layout, L, x, y) == species;
+    uint32_t pi = me ? (uint32_t)i : kNone;
+    if (runs) {
+      const uint64_t other = __ballot(!me), row0 = __ballot(me && x == 0);
+      const uint32_t lane = (uint32_t)(i & 63u);
+      const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane
+      const uint64_t bo = other & upto, bz = row0 & upto;
+      // one past the last lane of another species, and the last row start
+      const uint32_t so = bo ? 64u - (uint32_t)__clzll((long long)bo) : 0u;
+      const uint32_t sz = bz ? 63u - (uint32_t)__clzll((long long)bz) : 0u;
+      if (me) pi = (uint32_t)i - (lane - max(so, sz));
+    }
+    parent[i] = pi;
     size[i] = 0u;
   }
   for (size_t i = tid; i < (size_t)kSmallSizes; i += nth) hist[i] = 0u;
@@ -214,7 +235,10 @@ __device__ __forceinline__ void ccl_merge_body(const void* lat, int layout, int 
     const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
     if (site_bit(lat, layout, L, x, y) != species) continue;
     const int xr = (x + 1 == L) ? 0 : x + 1, yd = (y + 1 == L) ? 0 : y + 1;
-    if (site_bit(lat, layout, L, xr, y) == species) unite(parent, (uint32_t)i, (uint32_t)((size_t)y * L + xr));
+    // within a row and a 64-site segment the bond to the right is already a
+    // link of the initial runs
+    if ((xr == 0 || (i & 63u) == 63u) && site_bit(lat, layout, L, xr, y) == species)
+      unite(parent, (uint32_t)i, (uint32_t)((size_t)y * L + xr));
     if (site_bit(lat, layout, L, x, yd) == species) unite(parent, (uint32_t)i, (uint32_t)((size_t)yd * L + x));
   }
 }
@@ -310,10 +334,10 @@ __device__ __forceinline__ void ccl_hist_body(const uint32_t* size, int L, int H
 // The passes as kernels for one lattice (grid-stride over blockIdx.x), and
 // for many square lattices at once: replica blockIdx.y of a table, each with
 // its own buffers, the same grid-stride over blockIdx.x.
-__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species,
+__global__ __launch_bounds__(256) void ccl_init(const void* lat, int layout, int L, int H, int species, int runs,
                                                 uint32_t* parent, uint32_t* size, unsigned* hist,
                                                 unsigned* big_count) {
-  ccl_init_body(lat, layout, L, H, species, parent, size, hist, big_count);
+  ccl_init_body(lat, layout, L, H, species, runs != 0, parent, size, hist, big_count);
 }
 __global__ __launch_bounds__(256) void ccl_merge(const void* lat, int layout, int L, int species, uint32_t* parent) {
   ccl_merge_body(lat, layout, L, species, parent);
@@ -329,7 +353,7 @@ __global__ __launch_bounds__(256) void ccl_hist(const uint32_t* size, int L, int
 }
 __global__ __launch_bounds__(256) void ccl_init_many(const CclRep* reps, int species) {
   const CclRep& r = reps[blockIdx.y];
-  ccl_init_body(r.lat, r.layout, r.L, r.L, species, r.b.parent, r.b.size, r.b.hist, r.b.big_count);
+  ccl_init_body(r.lat, r.layout, r.L, r.L, species, true, r.b.parent, r.b.size, r.b.hist, r.b.big_count);
 }
 __global__ __launch_bounds__(256) void ccl_merge_many(const CclRep* reps, int species) {
   const CclRep& r = reps[blockIdx.y];
@@ -430,8 +454,8 @@ hipError_t launch_ccl(const void* lat, int layout, int L, int H, int species, co
                       hipStream_t stream) {
   const size_t n = (size_t)L * H;
   const int g = grid_for(n, 256);
-  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, H, species, b.parent, b.size, b.hist,
-                     b.big_count);
+  hipLaunchKernelGGL(ccl_init, dim3(g), dim3(256), 0, stream, lat, layout, L, H, species, triangular ? 0 : 1,
+                     b.parent, b.size, b.hist, b.big_count);
   if (triangular) {
     hipLaunchKernelGGL(ccl_merge_tri, dim3(g), dim3(256), 0, stream, static_cast<const uint8_t*>(lat), L, H, species,
                        b.parent);
